@@ -1,0 +1,540 @@
+"""Pins of the reference oracle against what the paper and the mathematics fix.
+
+None of these tests re-types the oracle's formulas: each compares the oracle
+with an independent definition (exact rational arithmetic, the B-spline
+definition of TSC, closed-form orbits, conservation laws, values printed in
+the paper) so that a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+# --------------------------------------------------------------------------
+# fixed-point quantiser: round-half-even of the exact product
+# --------------------------------------------------------------------------
+
+def _rne_fraction(x: Fraction) -> int:
+    fl = math.floor(x)
+    r = x - fl
+    if r > Fraction(1, 2):
+        return fl + 1
+    if r < Fraction(1, 2):
+        return fl
+    return fl if fl % 2 == 0 else fl + 1
+
+
+def test_quantize_equals_exact_rational_rne():
+    rng = np.random.default_rng(7)
+    for _ in range(4000):
+        W = float(rng.uniform(0.0, 1.0))
+        V = float(rng.uniform(-1.0, 1.0)) * 2.0 ** int(rng.integers(-5, 51))
+        assert O.quantize(W, V) == _rne_fraction(Fraction(W) * Fraction(V))
+
+
+def test_quantize_ties_go_to_even():
+    # products that are exactly k + 1/2
+    for k in range(-40, 40):
+        V = float(2 * k + 1)          # W = 1/2 -> (2k+1)/2 exact tie
+        assert O.quantize(0.5, V) == _rne_fraction(Fraction(2 * k + 1, 2))
+        assert O.quantize(0.5, V) % 2 == 0
+    # tie at a large magnitude
+    V = float(2 ** 50 + 1)
+    assert O.quantize(0.5, V) == _rne_fraction(Fraction(2 ** 50 + 1, 2))
+
+
+def test_quantize_sign_symmetry_and_zero():
+    rng = np.random.default_rng(8)
+    for _ in range(500):
+        W = float(rng.uniform(0.0, 1.0))
+        V = float(rng.uniform(0.0, 2.0 ** 45))
+        assert O.quantize(W, -V) == -O.quantize(W, V)
+    assert O.quantize(0.0, 123.0) == 0
+    assert O.quantize(0.3, 0.0) == 0
+
+
+# --------------------------------------------------------------------------
+# TSC weights: the quadratic B-spline (Sec. 3)
+# --------------------------------------------------------------------------
+
+def _bspline2(x: Fraction) -> Fraction:
+    """Quadratic B-spline of unit width, the TSC shape (textbook definition)."""
+    ax = abs(x)
+    if ax <= Fraction(1, 2):
+        return Fraction(3, 4) - ax * ax
+    if ax <= Fraction(3, 2):
+        return (Fraction(3, 2) - ax) ** 2 / 2
+    return Fraction(0)
+
+
+@pytest.mark.parametrize("num", list(range(-32, 32)))
+def test_tsc_weights_match_bspline_on_dyadic_offsets(num):
+    d = Fraction(num, 64)
+    w = O.tsc_weights(float(d))
+    for j, off in enumerate((-1, 0, 1)):
+        # weight of the cell at offset `off` from the nearest centre
+        assert Fraction(w[j]) == _bspline2(Fraction(off) - d)
+
+
+def test_tsc_weights_partition_of_unity_and_symmetry():
+    rng = np.random.default_rng(9)
+    for d in rng.uniform(-0.5, 0.5, size=2000):
+        w = O.tsc_weights(d)
+        assert abs(w.sum() - 1.0) <= 4 * np.finfo(float).eps
+        wm = O.tsc_weights(-d)
+        assert w[0] == wm[2] and w[1] == wm[1]
+        assert (w >= 0).all()
+
+
+# --------------------------------------------------------------------------
+# kinematics: worked numbers printed in the paper (Sec. 7, App. B.1)
+# --------------------------------------------------------------------------
+
+def test_lorentz_reduced_c_worked_numbers():
+    # run R2-REL: v0 = 30, C = 10*sqrt(2)*v0; E_sh = v0^2/2
+    v0 = 30.0
+    C = 10.0 * math.sqrt(2.0) * v0
+    Esh = v0 * v0 / 2
+    # a particle with E_k = 10 E_sh: gamma ~ 1.025, four-velocity ~ 3.2 v0, u ~ 0.22 C
+    gam = 1.0 + 10 * Esh / (C * C)
+    vmag = C * math.sqrt(gam * gam - 1.0)
+    g, u, ek = O.lorentz([vmag, 0.0, 0.0], C)
+    assert abs(g - 1.025) < 5e-4
+    assert abs(ek / (10 * Esh) - 1.0) < 1e-12
+    assert abs(vmag / v0 - 3.2) < 0.05
+    assert abs(u[0] / C - 0.22) < 0.005
+    # transition energy E_k ~ C^2/2 ~ 200 E_sh has gamma ~ 1.5
+    vmag = C * math.sqrt(1.5 ** 2 - 1.0)
+    g, u, ek = O.lorentz([0.0, vmag, 0.0], C)
+    assert abs(g - 1.5) < 1e-12
+    assert abs(ek / (200 * Esh) - 1.0) < 1e-12
+
+
+def test_lorentz_gyration_test_numbers():
+    # App. B.1: C = 10, v_perp = 1 -> gamma_1 = sqrt(101)/10; v_perp = 100 -> ~10
+    g, u, ek = O.lorentz([0.0, 1.0, 0.0], 10.0)
+    assert abs(g - math.sqrt(101.0) / 10.0) < 1e-15
+    assert abs(u[1] - 10.0 / math.sqrt(101.0)) < 1e-15
+    g, u, ek = O.lorentz([0.0, 100.0, 0.0], 10.0)
+    assert abs(g - 10.0) < 0.06
+    # Omega_L = (qB/mc)/gamma ~ 0.1 for B0 = q/mc = 1
+    assert abs(1.0 / g - 0.1) < 0.001
+
+
+def test_kinetic_energy_two_forms_agree():
+    rng = np.random.default_rng(10)
+    for _ in range(200):
+        C = float(rng.uniform(1.0, 1e4))
+        v = rng.normal(size=3) * C * 10 ** rng.uniform(-3, 2)
+        g, u, ek = O.lorentz(v, C)
+        # (gamma - 1) C^2 with gamma from the other printed form C / sqrt(C^2 - u^2)
+        u2 = float(np.dot(u, u))
+        g2 = C / math.sqrt(C * C - u2)
+        assert abs(g2 / g - 1.0) < 1e-11
+        assert abs(ek - (g - 1.0) * C * C) <= 1e-9 * max(ek, 1e-300) + 1e-12 * C * C
+        assert np.allclose(u * g, v, rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Boris push in a pure magnetic field (App. A.2)
+# --------------------------------------------------------------------------
+
+def test_boris_pure_B_norm_and_rotation_angle():
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        C = float(rng.uniform(5.0, 100.0))
+        v = rng.normal(size=3) * float(rng.uniform(0.1, 3.0)) * C
+        B = rng.normal(size=3)
+        qm = float(rng.uniform(0.5, 2.0))
+        dt = float(rng.uniform(0.01, 1.0))
+        vn = O.boris_kick_rotate_kick(v, np.zeros(3), B, 0.5 * qm * dt, C)
+        # |v| is unchanged by a rotation
+        assert abs(np.linalg.norm(vn) / np.linalg.norm(v) - 1.0) < 4e-16 * 8
+        # the rotation angle about B is 2 atan(Omega_L dt / 2)
+        gam = math.sqrt(1.0 + np.dot(v, v) / C ** 2)
+        Bm = np.linalg.norm(B)
+        bh = B / Bm
+        vp = v - np.dot(v, bh) * bh
+        vnp = vn - np.dot(vn, bh) * bh
+        assert abs(np.dot(vn, bh) - np.dot(v, bh)) < 1e-12 * np.linalg.norm(v)
+        cosang = np.dot(vp, vnp) / (np.linalg.norm(vp) * np.linalg.norm(vnp))
+        sinang = np.dot(np.cross(vp, vnp), bh) / (np.linalg.norm(vp) * np.linalg.norm(vnp))
+        ang = math.atan2(sinang, cosang)
+        omega = qm * Bm / gam
+        # positive charge gyrates clockwise about B: angle is negative
+        assert abs(ang + 2.0 * math.atan(0.5 * omega * dt)) < 1e-10
+
+
+def test_boris_uniform_E_parallel_acceleration():
+    # E parallel to B with no perpendicular velocity: dv/dt = (q/mc) E exactly
+    C = 50.0
+    v = np.array([0.3, 0.0, 0.0])
+    E = np.array([0.7, 0.0, 0.0])
+    B = np.array([2.0, 0.0, 0.0])
+    vn = O.boris_kick_rotate_kick(v, E, B, 0.5 * 1.5 * 0.2, C)
+    assert abs(vn[0] - (0.3 + 1.5 * 0.2 * 0.7)) < 1e-15
+    assert vn[1] == 0.0 and vn[2] == 0.0
+
+
+def test_clean_E_removes_parallel_component():
+    rng = np.random.default_rng(12)
+    for _ in range(500):
+        E = rng.normal(size=3)
+        B = rng.normal(size=3)
+        Ec = O.clean_E(E, B)
+        assert abs(np.dot(Ec, B)) < 1e-14 * np.linalg.norm(E) * np.linalg.norm(B)
+        # the perpendicular part is untouched
+        bh = B / np.linalg.norm(B)
+        assert np.allclose(Ec, E - np.dot(E, bh) * bh, rtol=0, atol=1e-14)
+    E = np.array([1.0, 2.0, 3.0])
+    assert (O.clean_E(E, np.zeros(3)) == E).all()
+
+
+# --------------------------------------------------------------------------
+# whole-step orbits on a periodic grid with uniform fields (App. B.1)
+# --------------------------------------------------------------------------
+
+def _uniform_fields(box, Bvec, vgvec):
+    nc = box.n_cells
+    B = np.repeat(np.asarray(Bvec, float)[:, None], nc, axis=1).copy()
+    vg = np.repeat(np.asarray(vgvec, float)[:, None], nc, axis=1).copy()
+    rho = np.ones(nc)
+    return B, vg, rho
+
+
+def _unwrap_track(xs, L):
+    xs = np.array(xs)
+    out = xs.copy()
+    for i in range(1, len(xs)):
+        dlt = xs[i] - xs[i - 1]
+        dlt -= L * np.round(dlt / L)
+        out[i] = out[i - 1] + dlt
+    return out
+
+
+@pytest.mark.parametrize("vperp,dxc,base,amp", [(1.0, 4.0, 0.5, 0.1), (100.0, 64.0, 5.0, 1.0)])
+def test_gyration_variable_dt_circle_and_energy(vperp, dxc, base, amp):
+    """App. B.1 without drift: B0 = q/mc = 1, C = 10, dt = base + amp cos(alpha).
+    Full-step positions lie on a circle of radius R_L = v_perp / (qB0/mc) about
+    the guiding centre, and |v| (the energy) is conserved despite the
+    variable step."""
+    C = 10.0
+    box = O.Box(ndim=2, n=(16, 16, 1), dx=(dxc, dxc, 1.0), C=C)
+    B, vg, rho = _uniform_fields(box, (0.0, 0.0, 1.0), (0.0, 0.0, 0.0))
+    L = 16 * dxc
+    x = np.array([[0.37 * L], [0.61 * L], [0.0]])
+    v = np.array([[vperp], [0.0], [0.0]])
+    sys = O.System(box, x, v, np.array([1.0]), np.array([1.0]))
+    RL = vperp / 1.0
+    # u x B for u along +x, B along +z points along -y: centre at y - R_L
+    centre = np.array([x[0, 0], x[1, 0] - RL])
+    rng = np.random.default_rng(13)
+    track = [sys.positions()[:2, 0].copy()]
+    vnorm0 = np.linalg.norm(sys.v[:, 0])
+    for _ in range(400):
+        dt = base + amp * math.cos(rng.uniform(0, 2 * math.pi))
+        sys.step(B, vg, rho, dt, 1)
+        track.append(sys.positions()[:2, 0].copy())
+        assert abs(np.linalg.norm(sys.v[:, 0]) / vnorm0 - 1.0) < 1e-13
+    tr = _unwrap_track(track, L)
+    r = np.sqrt(((tr - centre[None, :]) ** 2).sum(axis=1))
+    assert np.abs(r / RL - 1.0).max() < 1e-11
+
+
+def _drift_gyration_eprime(dts):
+    """App. B.1 with a drifting gas, v0 = 1 along y, C = 10, B0 = q/mc = 1 along
+    x in the co-moving frame.  Returns E'(t)/E'(0) - 1, with E' the kinetic
+    energy in the co-moving frame."""
+    C = 10.0
+    v0 = 1.0
+    box = O.Box(ndim=2, n=(32, 32, 1), dx=(4.0, 4.0, 1.0), C=C)
+    # lab frame: E = -v_g x B
+    B, vg, rho = _uniform_fields(box, (1.0, 0.0, 0.0), (0.0, v0, 0.0))
+    g0 = C / math.sqrt(C * C - v0 * v0)
+    # particle: v_par = 0, v_perp = 1 (along z) in the co-moving frame,
+    # boosted to the lab frame (relative velocity v0 along y)
+    vp = np.array([0.0, 0.0, 1.0])
+    gp = math.sqrt(1.0 + np.dot(vp, vp) / C ** 2)
+    vlab = vp.copy()
+    vlab[1] = g0 * (vp[1] + v0 * gp)
+    x = np.array([[40.0], [20.0], [0.0]])
+    sys = O.System(box, x, vlab[:, None].copy(), np.array([1.0]), np.array([1.0]))
+
+    def eprime():
+        v = sys.v[:, 0]
+        g = math.sqrt(1.0 + np.dot(v, v) / C ** 2)
+        gpr = g0 * (g - v0 * v[1] / C ** 2)
+        return (gpr - 1.0) * C * C
+
+    e_init = eprime()
+    devs = []
+    for dt in dts:
+        sys.step(B, vg, rho, dt, 1)
+        devs.append(eprime() / e_init - 1.0)
+    return np.array(devs)
+
+
+def test_gyration_with_drift_energy_oscillation_level():
+    """With a drifting gas E' is no longer conserved: it oscillates at the
+    0.1 % level for Omega_L dt = 0.5 (App. B.1), and the oscillation is a
+    truncation error of second order in dt."""
+    d1 = _drift_gyration_eprime([0.5] * 120)
+    d2 = _drift_gyration_eprime([0.25] * 240)
+    a1 = 0.5 * (d1.max() - d1.min())
+    a2 = 0.5 * (d2.max() - d2.min())
+    assert 3e-4 < a1 < 3e-3
+    assert 3.0 < a1 / a2 < 5.0
+    # the variable step of the paper's test adds a random-walk drift but stays
+    # at the sub-percent level over 300 steps
+    rng = np.random.default_rng(14)
+    dts = [0.5 + 0.1 * math.cos(rng.uniform(0, 2 * math.pi)) for _ in range(300)]
+    assert np.abs(_drift_gyration_eprime(dts)).max() < 1e-2
+
+
+def test_exb_drift_second_order():
+    """Uniform B along z and gas velocity v_g along y: the guiding centre moves
+    with v_g (the E x B velocity) up to an O(dt^2) error (App. A.2)."""
+    C = 100.0
+    vdrift = 0.5
+
+    def measured(dt):
+        box = O.Box(ndim=2, n=(16, 16, 1), dx=(64.0, 64.0, 1.0), C=C)
+        B, vg, rho = _uniform_fields(box, (0.0, 0.0, 1.0), (0.0, vdrift, 0.0))
+        x = np.array([[100.0], [100.0], [0.0]])
+        v = np.array([[2.0], [0.0], [0.0]])
+        sys = O.System(box, x, v, np.array([1.0]), np.array([1.0]))
+        L = 16 * 64.0
+        # gyro-centre from the state: x_gc = x + (u - v_E) x B / (Omega B)
+        def gc():
+            xx = sys.positions()[:2, 0]
+            vv = sys.v[:, 0]
+            g = math.sqrt(1.0 + np.dot(vv, vv) / C ** 2)
+            u = vv / g
+            w = u - np.array([0.0, vdrift, 0.0])
+            # (w x zhat) * gamma / (q/mc B)
+            return np.array([xx[0] + w[1] * g, xx[1] - w[0] * g])
+
+        T = 200.0
+        nst = int(round(T / dt))
+        track = [gc()]
+        for _ in range(nst):
+            sys.step(B, vg, rho, dt, 1)
+            track.append(gc())
+        tr = _unwrap_track(track, L)
+        t = np.arange(len(tr)) * dt
+        slope = np.polyfit(t, tr[:, 1], 1)[0]
+        return slope
+
+    e1 = abs(measured(0.2) - vdrift)
+    e2 = abs(measured(0.1) - vdrift)
+    assert e1 < 2e-6 * vdrift
+    assert 3.5 < e1 / e2 < 4.5
+
+
+def test_time_reversibility():
+    from paper_1412_1087_amd import workloads as W
+    wl = W.gyro2d(nx=8, ny=8, ppc=4, seed=17)
+    box = O.Box(ndim=2, n=wl.box.n, C=wl.box.C, hall=0)
+    sys = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    x0 = sys.positions().copy()
+    v0 = sys.v.copy()
+    sys.step(wl.B, wl.vg, wl.rho, wl.dt, 40)
+    assert np.abs(sys.v - v0).max() > 1e-3
+    sys.step(wl.B, wl.vg, wl.rho, -wl.dt, 40)
+    L = np.array([8.0, 8.0, 1.0])[:, None]
+    dx = sys.positions() - x0
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < 1e-10
+    assert np.abs(sys.v - v0).max() < 1e-10 * np.abs(v0).max()
+
+
+# --------------------------------------------------------------------------
+# cell-centred fields with the CR-Hall term (Sec. 2.1)
+# --------------------------------------------------------------------------
+
+def _random_cells(nc, rng):
+    B = rng.normal(size=(3, nc))
+    vg = rng.normal(size=(3, nc))
+    rho = rng.uniform(0.5, 2.0, size=nc)
+    return B, vg, rho
+
+
+def test_fieldprep_hall_identities():
+    rng = np.random.default_rng(15)
+    box = O.Box(ndim=2, n=(8, 4, 1), hall=1, qomc_gas=1.3, frac_bits=40)
+    nc = box.n_cells
+    B, vg, rho = _random_cells(nc, rng)
+    D = np.zeros((8, nc), dtype=np.int64)
+    # n_CR ~ 0.05 n_g, u_CR ~ 10 in amount units of 2^-40
+    n = 0.05 * 1.3 * rho * rng.uniform(0.5, 1.5, size=nc)
+    ucr = rng.normal(size=(3, nc)) * 10.0
+    D[0] = np.round(n * 2.0 ** 40).astype(np.int64)
+    D[1:4] = np.round(n * ucr * 2.0 ** 40).astype(np.int64)
+    E = O.fieldprep(box, B, vg, rho, D)
+    nq = D[0] / 2.0 ** 40
+    J = D[1:4] / 2.0 ** 40
+    ng = 1.3 * rho
+    R = nq / (ng + nq)
+    u_cr = J / nq
+    # eq. emfcr1: E = -[(1-R) v_g + R u_CR] x B
+    adv = (1 - R) * vg + R * u_cr
+    E1 = -np.cross(adv.T, B.T).T
+    scale = np.linalg.norm(adv, axis=0) * np.linalg.norm(B, axis=0)
+    assert (np.linalg.norm(E - E1, axis=0) <= 1e-13 * scale).all()
+    # eq. emfcr0: E = -v_g x B - (n_CR/|n_e|)(u_CR - v_g) x B, |n_e| = n_g + n_CR
+    E0 = -np.cross(vg.T, B.T).T - (nq / (ng + nq)) * np.cross((u_cr - vg).T, B.T).T
+    assert (np.linalg.norm(E - E0, axis=0) <= 1e-13 * scale).all()
+    # E . B = 0 at cell centres
+    assert (np.abs((E * B).sum(axis=0)) <= 1e-13 * scale * np.linalg.norm(B, axis=0)).all()
+    # eq. eng: v_g . F_CR = J_CR . E, with F_CR = n_g (E0 - E)
+    E0 = -np.cross(vg.T, B.T).T
+    F = ng * (E0 - E)
+    lhs = (vg * F).sum(axis=0)
+    rhs = (J * E).sum(axis=0)
+    mag = np.linalg.norm(vg, axis=0) * np.linalg.norm(F, axis=0) + np.linalg.norm(J, axis=0) * \
+        np.linalg.norm(E, axis=0)
+    assert (np.abs(lhs - rhs) <= 1e-12 * mag).all()
+
+
+def test_fieldprep_without_hall_is_ideal_mhd():
+    rng = np.random.default_rng(16)
+    box = O.Box(ndim=3, n=(4, 3, 2), hall=0)
+    nc = box.n_cells
+    B, vg, rho = _random_cells(nc, rng)
+    D = rng.integers(-2 ** 40, 2 ** 40, size=(8, nc)).astype(np.int64)
+    E = O.fieldprep(box, B, vg, rho, D)
+    E0 = -np.cross(vg.T, B.T).T
+    assert np.allclose(E, E0, rtol=0, atol=1e-14 * np.abs(E0).max())
+
+
+# --------------------------------------------------------------------------
+# deposits: placement, conservation, uniformity, order independence
+# --------------------------------------------------------------------------
+
+def test_single_particle_deposit_matches_bspline_and_wraps():
+    """One particle near a corner of a small periodic 3D box: each stencil
+    cell receives the exact B-spline weight times the amount, to within half a
+    quantum plus the weight's own rounding, and the integers sum to the
+    rounded amount exactly."""
+    box = O.Box(ndim=3, n=(4, 5, 3), C=20.0, frac_bits=40)
+    nc = box.n_cells
+    x = np.array([[0.1], [4.93], [1.5 + 0.2]])
+    v = np.array([[3.0], [-1.0], [2.0]])
+    m, qm = np.array([0.0123]), np.array([1.7])
+    sys = O.System(box, x, v, m, qm)
+    D = sys.D
+    S = 2.0 ** 40
+    Vn = (1.7 * 0.0123) * S
+    # exact expected weights from the B-spline, nearest centre by coordinates
+    expect = np.zeros(nc)
+    pos = [Fraction(0.1), Fraction(4.93), Fraction(1.7)]
+    for cz in range(3):
+        for cy in range(5):
+            for cx in range(4):
+                w = Fraction(1)
+                for d, (c, nn) in enumerate(zip((cx, cy, cz), (4, 5, 3))):
+                    # periodic distance from the particle to the centre of cell c
+                    dist = pos[d] - (c + Fraction(1, 2))
+                    dist -= nn * round(dist / nn)
+                    w *= _bspline2(dist)
+                expect[(cz * 5 + cy) * 4 + cx] = float(w * Fraction(Vn))
+    assert D[0].sum() == _rne_fraction(Fraction(Vn))
+    nz = np.nonzero(expect)[0]
+    assert len(nz) == 27
+    assert set(np.nonzero(D[0])[0]) <= set(nz)
+    # non-centre cells: round-half-even of the product, off by at most half a
+    # quantum plus the weight's rounding; the centre (cell (0,4,1)) takes the
+    # remainder and so carries the other 26 roundings as well
+    centre = (1 * 5 + 4) * 4 + 0
+    err = np.abs(D[0] - expect)
+    assert np.delete(err, centre).max() <= 0.5 + Vn * 2.0 ** -49
+    assert err[centre] <= 0.5 * 27 + Vn * 2.0 ** -48
+    # accumulated channels start at zero
+    assert (D[4:] == 0).all()
+
+
+def test_uniform_lattice_load_deposits_uniformly():
+    from paper_1412_1087_amd import workloads as W
+    box = O.Box(ndim=3, n=(6, 5, 4), C=20.0, hall=1)
+    nc = box.n_cells
+    # one particle per cell at the same offset with the same velocity
+    cz, cy, cx = np.meshgrid(np.arange(4), np.arange(5), np.arange(6), indexing="ij")
+    x = np.stack([cx.ravel() + 0.5 + 0.31, cy.ravel() + 0.5 - 0.17, cz.ravel() + 0.5 + 0.05])
+    N = x.shape[1]
+    v = np.repeat(np.array([[4.0], [-2.5], [1.25]]), N, axis=1)
+    m = np.full(N, 0.01)
+    qm = np.full(N, 1.0)
+    sys = O.System(box, x, v, m, qm)
+    for ch in range(4):
+        assert (sys.D[ch] == sys.D[ch][0]).all()
+    B = np.repeat(np.array([[0.8], [0.3], [-0.4]]), nc, axis=1)
+    vg = np.repeat(np.array([[0.2], [0.1], [0.0]]), nc, axis=1)
+    rho = np.ones(nc)
+    sys.step(B, vg, rho, 0.05, 3)
+    for ch in range(8):
+        assert (sys.D[ch] == sys.D[ch][0]).all(), ch
+    assert (sys.D[4:] != 0).any()
+
+
+def _rne_float(V: float) -> int:
+    return _rne_fraction(Fraction(V))
+
+
+@pytest.mark.parametrize("hall", [0, 1])
+def test_deposits_conserve_momentum_energy_charge_exactly(hall):
+    """The integers deposited for -dM sum over the grid to the particles'
+    rounded momentum change, exactly (App. A.3: the gas receives the opposite
+    of the CR change); charge sums to the particles' rounded charge."""
+    from paper_1412_1087_amd import workloads as W
+    wl = W.bell3d(n=(6, 5, 4), ppc=3, seed=21, hall=hall)
+    box = O.Box(ndim=3, n=wl.box.n, C=wl.box.C, hall=hall)
+    sys = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    S = 2.0 ** 40
+    v_before = sys.v.copy()
+    sys.step(wl.B, wl.vg, wl.rho, wl.dt, 1)
+    v_after = sys.v
+    for d in range(3):
+        amounts = -(wl.m * (v_after[d] - v_before[d])) * S
+        want = sum(_rne_float(a) for a in amounts)
+        assert int(sys.D[4 + d].sum()) == want
+        # and within rounding of the exact real change
+        assert abs(int(sys.D[4 + d].sum()) - amounts.sum()) <= 0.5 * wl.N + 1e-9 * np.abs(amounts).sum()
+    # energy: the gas receives minus the CR kinetic-energy change, (gamma-1) C^2 form
+    C = wl.box.C
+    g0 = np.sqrt(1.0 + (v_before ** 2).sum(axis=0) / C ** 2)
+    g1 = np.sqrt(1.0 + (v_after ** 2).sum(axis=0) / C ** 2)
+    dEk = (wl.m * (g1 - g0) * C * C).sum() * S
+    assert abs(int(sys.D[7].sum()) + dEk) <= 1e-6 * abs(dEk) + wl.N
+    # charge and current at the new positions
+    assert int(sys.D[0].sum()) == sum(_rne_float(a) for a in (wl.qm * wl.m) * S)
+    u1 = v_after / g1
+    for d in range(3):
+        want = ((wl.qm * wl.m) * u1[d] * S).sum()
+        assert abs(int(sys.D[1 + d].sum()) - want) <= wl.N + 1e-12 * np.abs(want)
+
+
+def test_deposit_and_states_independent_of_particle_order():
+    from paper_1412_1087_amd import workloads as W
+    wl = W.gyro2d(nx=8, ny=6, ppc=5, seed=22)
+    box = O.Box(ndim=2, n=wl.box.n, C=wl.box.C)
+    a = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    perm = np.random.default_rng(3).permutation(wl.N)
+    b = O.System(box, wl.x[:, perm], wl.v[:, perm], wl.m[perm], wl.qm[perm])
+    a.step(wl.B, wl.vg, wl.rho, wl.dt, 5)
+    b.step(wl.B, wl.vg, wl.rho, wl.dt, 5)
+    assert (a.D == b.D).all()
+    assert (a.v[:, perm] == b.v).all()
+    assert (a.positions()[:, perm] == b.positions()).all()
+
+
+def test_move_limit_is_enforced():
+    box = O.Box(ndim=2, n=(8, 8, 1), C=20.0, max_move_cells=2)
+    assert O.check_dt(box, 0.099) == O.OK
+    assert O.check_dt(box, 0.1001) == O.ERANGE
+    box1 = O.Box(ndim=2, n=(8, 8, 1), C=20.0, max_move_cells=1)
+    assert O.check_dt(box1, 0.0501) == O.ERANGE
