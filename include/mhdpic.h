@@ -1,0 +1,153 @@
+/*
+ * mhdpic.h -- C ABI of the MI355X cosmic-ray particle step of the MHD-PIC
+ * method (Bai, Caprioli, Sironi & Spitkovsky 2015).
+ *
+ * One call of mhdpic_step advances every CR particle by one or more steps
+ * through fields held fixed during the call:
+ *   - gather: the cell-centred B and E = E0 - F_CR/n_g (E0 = -v_g x B, the
+ *     CR-Hall correction of Sec. 2.1, eq. emfcr2, optional) are interpolated to
+ *     the particle at x^(n+1/2) with TSC (quadratic-spline) weights (Sec. 3);
+ *   - push: drift-kick-rotate-kick-drift relativistic Boris step at the
+ *     reduced speed of light C, with the parallel electric field removed at
+ *     the particle (App. A.2);
+ *   - deposit: -dM = -m(v^(n+1)-v^(n)) and -dE_k = -m(E_k^(n+1)-E_k^(n)) at
+ *     x^(n+1/2) (App. A.3, corrector), and n_CR = (q/mc) m, J_CR = (q/mc) m u
+ *     at x^(n+1) (App. A.1 eq. nJCR; the predictor input of the next step).
+ *
+ * Deposits are exact 64-bit fixed-point amounts in units of 2^-frac_bits:
+ * a stencil cell k other than the particle's own receives
+ * round-half-even(W_k * V) of the exact product, and the particle's own cell
+ * receives round-half-even(V) minus the others, so sums are exact and do not
+ * depend on the order in which particles are processed.  Integers wrap
+ * modulo 2^64.  Divide an amount by 2^frac_bits and by the cell volume to get
+ * a density.
+ *
+ * Conventions for every entry point:
+ *   - Array pointers named "device" are HIP device pointers.  Arrays are
+ *     structure-of-arrays with the component outermost: a [3][N] array holds
+ *     all x-components, then y, then z.  Grid arrays are [comp][cells] with the
+ *     cells of box 0 first, then box 1, ...; within a box x is fastest:
+ *     cell = (iz*ny + iy)*nx + ix.  Particle arrays hold box 0's particles
+ *     first, then box 1's, ...
+ *   - The caller owns all memory, including the workspace.  The library keeps
+ *     only descriptors into it; the workspace must stay allocated and untouched
+ *     until mhdpic_destroy.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it and the call returns without waiting, except where a
+ *     function says otherwise.  Inputs must stay valid until the stream has
+ *     passed the call's work.
+ *   - Errors are returned as the codes below; nothing is thrown across the
+ *     ABI.  mhdpic_last_error() gives a message for the last failure of the
+ *     calling thread.  A condition found by a kernel (non-finite velocity,
+ *     an amount too large for the fixed point) is latched on the device and
+ *     returned by mhdpic_check, or by the next mhdpic_step once the earlier
+ *     work has finished.
+ */
+#ifndef MHDPIC_H
+#define MHDPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MHDPIC_OK = 0,
+    MHDPIC_EINVAL = -1,     /* bad argument */
+    MHDPIC_ENOMEM = -2,     /* workspace too small */
+    MHDPIC_EDEVICE = -3,    /* a HIP call failed */
+    MHDPIC_ERANGE = -4,     /* time step over the move limit, a deposit amount
+                               |V| >= 2^51 quanta, or a grid/particle count
+                               beyond the library's index limits */
+    MHDPIC_ENONFINITE = -5, /* a position or velocity is not finite */
+    MHDPIC_ESTATE = -6,     /* internal consistency check failed */
+    MHDPIC_ENOTSUP = -7     /* configuration not supported by this build */
+};
+
+enum { MHDPIC_FP64 = 0, MHDPIC_FP32_MIXED = 1 };
+
+/* One periodic box of the grid (units: the paper's code units, Sec. 5.1). */
+typedef struct {
+    int32_t ndim;           /* 2 or 3; every box of one context has the same ndim */
+    int32_t n[3];           /* cells per dimension; n[2] must be 1 in 2D.
+                               Limits: 3D nx,ny <= 2048, nz <= 1024; 2D nx,ny <= 65536 */
+    double dx[3];           /* cell size per dimension (> 0) */
+    double x0[3];           /* lower corner */
+    double C;               /* reduced particle speed of light (Sec. 2.2), > 0 */
+    double qomc_gas;        /* (q/mc)_g of the gas ions: n_g = qomc_gas * rho (App. A.1, eq. ng) */
+    int32_t hall;           /* 1: E = E0 - F_CR/n_g (Sec. 2.1, eq. emfcr2); 0: E = E0 */
+    int32_t frac_bits;      /* fixed-point quantum 2^-frac_bits, 0..60 (40 is the usual value) */
+    int32_t max_move_cells; /* 1 or 2: a particle crosses at most this many cells per step
+                               (App. A.4); mhdpic_step rejects C*|dt|/dx above it */
+    int32_t tile[3];        /* cells per tile per dimension for the LDS-staged kernels;
+                               0 = library default.  tile[2] is ignored in 2D */
+} mhdpic_box;
+
+typedef struct mhdpic_ctx mhdpic_ctx;
+
+/* Bytes of device workspace a context needs for these boxes, particle counts
+ * (n_particles[b] for box b) and precision (MHDPIC_FP64 or MHDPIC_FP32_MIXED). */
+int mhdpic_workspace_size(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                          int32_t precision, size_t* bytes);
+
+/* Creates a context: converts the particles' global positions to (cell index,
+ * offset from the cell centre) form, and deposits n_CR and J_CR at the initial
+ * positions (App. A.3 predictor).  The accumulated -dM, -dE_k start at zero.
+ *   x, v   device, [3][N] doubles: global positions (2D ignores z) and spatial
+ *          four-velocities v = gamma*u (Sec. 2.2, eq. 4vel)
+ *   m, qm  device, [N] doubles: the CR mass carried by each particle and its
+ *          (q/mc) (App. A.1)
+ *   workspace  device, at least mhdpic_workspace_size bytes, 256-byte aligned
+ * N is the sum of n_particles.  The call waits for the stream before it
+ * returns (it checks the converted input). */
+int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                int32_t precision, const double* x, const double* v, const double* m,
+                const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
+                mhdpic_ctx** out);
+
+/* Advances all particles n_steps steps (App. A.2, A.3) through fixed fields.
+ *   B, vg  device, [3][cells] doubles: cell-centred magnetic field and gas velocity
+ *   rho    device, [cells] doubles: gas density (read only where hall = 1)
+ *   dt     host, [n_boxes] doubles: time step of each box (may be negative)
+ * Before each step the cell-centred E is formed from the current n_CR, J_CR
+ * (Sec. 2.1); -dM and -dE_k accumulate over steps; n_CR and J_CR are replaced
+ * by their values at the new positions.  Returns MHDPIC_ERANGE if
+ * C*|dt|/dx > max_move_cells for any box.  Does not wait for the stream. */
+int mhdpic_step(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
+                const double* dt, int32_t n_steps, void* hip_stream);
+
+/* Copies the deposits to out (device, [8][cells] int64): channels
+ * 0..3 = n_CR, J_CR x,y,z at the current positions; 4..6 = accumulated
+ * -dM x,y,z; 7 = accumulated -dE_k.  If reset_accumulated is nonzero,
+ * channels 4..7 are cleared after the copy.  Does not wait. */
+int mhdpic_deposit_read(mhdpic_ctx* ctx, int64_t* out, int32_t reset_accumulated,
+                        void* hip_stream);
+
+/* Copies particle states to x, v (device, [3][N] doubles) in the original
+ * particle order: global positions x0 + dx*((i + 1/2) + offset) (z = 0 in
+ * 2D) and four-velocities.  Does not wait. */
+int mhdpic_particles_read(mhdpic_ctx* ctx, double* x, double* v, void* hip_stream);
+
+/* Waits for the stream and returns the latched device error (then clears it):
+ * MHDPIC_OK, MHDPIC_ENONFINITE, MHDPIC_ERANGE or MHDPIC_ESTATE. */
+int mhdpic_check(mhdpic_ctx* ctx, void* hip_stream);
+
+/* Frees the context's host-side state.  The workspace is the caller's. */
+int mhdpic_destroy(mhdpic_ctx* ctx);
+
+/* Message for the last non-OK code returned on the calling thread. */
+const char* mhdpic_last_error(void);
+
+/* Arithmetic self-test: out[0][i] = sqrt(a[i]), out[1][i] = a[i]/b[i],
+ * out[2][i] = fma(a[i], b[i], c[i]), out[3][i] = (double)(int64)bits of c[i]
+ * reinterpreted, computed by the device with the rounding the step kernels
+ * use.  a, b, c device [n] doubles; out device [4][n].  Waits for the stream. */
+int mhdpic_selftest_arith(const double* a, const double* b, const double* c, double* out,
+                          int64_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,91 @@
+// Device-side data structures shared by the kernels and the host runtime of
+// the MHD-PIC cosmic-ray particle library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mhdpic {
+
+// Error bits latched by kernels in the device error word.
+enum : uint32_t {
+    ERRBIT_NONFINITE = 1u,  // a velocity or position became non-finite
+    ERRBIT_RANGE = 2u,      // a deposit amount |V| >= 2^51 quanta
+    ERRBIT_STATE = 4u,      // a particle was not inside the tile it was binned to
+};
+
+// 1.5 * 2^52: adding a double of magnitude < 2^51 to it rounds that double to
+// an integer (round-half-even) held exactly in the low mantissa bits.  The
+// low 32 bits of its bit pattern are zero.
+constexpr double kMagic = 6755399441055744.0;
+constexpr uint32_t kMagicHi = 0x43380000u;
+constexpr double kMaxAmount = 2251799813685248.0;  // 2^51
+
+// Box descriptor as the kernels see it.  Per-call fields (dt, hdt, hdx) are
+// refreshed by mhdpic_step before its kernels are enqueued.
+struct BoxDev {
+    int32_t n[3];      // cells per dimension (n[2] = 1 in 2D)
+    int32_t nt[3];     // tiles per dimension
+    int32_t tile_off;  // global index of this box's first tile
+    int32_t hall;
+    int64_t cell_off;  // global index of this box's first cell
+    int64_t part_off;  // first particle slot of this box
+    int64_t part_n;    // particles in this box
+    double dx[3];
+    double x0[3];
+    double C, C2, iC;  // C, C*C, 1/C
+    double qg;         // (q/mc) of the gas ions
+    double S, iS;      // 2^frac_bits, 2^-frac_bits
+    double dV;         // cell volume
+    double dt, hdt;    // step and half step of the current call
+    double hdx[3];     // hdt / dx[d]
+};
+
+// Particle store, structure of arrays.  cell holds the packed cell indices
+// (2D: ix | iy<<16; 3D: ix | iy<<11 | iz<<22); d holds the offsets from the
+// cell centre in cell units; v the spatial four-velocity gamma*u.
+struct PartF64 {
+    uint32_t* cell;
+    double* d[3];
+    double* v[3];
+    double* m;
+    double* qm;
+    int32_t* pid;
+};
+
+// Precision form: every per-particle value in single precision.
+struct PartF32 {
+    uint32_t* cell;
+    float* d[3];
+    float* v[3];
+    float* m;
+    float* qm;
+    int32_t* pid;
+};
+
+struct WorkItem {
+    int32_t tile;   // global tile index
+    int32_t begin;  // first particle slot
+    int32_t end;    // one past the last slot
+    int32_t box;
+};
+
+template <int NDIM>
+__host__ __device__ inline uint32_t pack_cell(int ix, int iy, int iz) {
+    if (NDIM == 2) return (uint32_t)ix | ((uint32_t)iy << 16);
+    return (uint32_t)ix | ((uint32_t)iy << 11) | ((uint32_t)iz << 22);
+}
+
+template <int NDIM>
+__host__ __device__ inline void unpack_cell(uint32_t c, int& ix, int& iy, int& iz) {
+    if (NDIM == 2) {
+        ix = (int)(c & 0xFFFFu);
+        iy = (int)(c >> 16);
+        iz = 0;
+    } else {
+        ix = (int)(c & 0x7FFu);
+        iy = (int)((c >> 11) & 0x7FFu);
+        iz = (int)(c >> 22);
+    }
+}
+
+}  // namespace mhdpic

@@ -1,0 +1,357 @@
+// HIP kernels of the MHD-PIC cosmic-ray particle step (binary64 form and
+// shared bookkeeping).  gfx950: wave64, 160 KB LDS per CU, 8 XCDs.
+#pragma once
+#include "arith.h"
+#include "common.h"
+
+namespace mhdpic {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ void latch(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+
+// Box that owns global index g, given ascending offsets off[0..nb] (off[nb] = total).
+__device__ __forceinline__ int find_box(const int64_t* off, int nb, int64_t g) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Every lane of the wave must call this (no divergence at the call site).
+// Returns, for active lanes, a distinct slot obtained from counters[key]; one
+// atomic per distinct key in the wave.
+__device__ __forceinline__ uint32_t wave_claim(uint32_t* counters, uint32_t key, bool active) {
+    uint64_t pending = __ballot(active);
+    uint32_t slot = 0;
+    const int lane = lane_id();
+    while (pending) {
+        int leader = __ffsll((unsigned long long)pending) - 1;
+        uint32_t k = __shfl(key, leader);
+        uint64_t grp = __ballot(active && key == k) & pending;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counters[k], (uint32_t)__popcll(grp));
+        base = __shfl(base, leader);
+        if ((grp >> lane) & 1ull) slot = base + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        pending &= ~grp;
+    }
+    return slot;
+}
+
+__device__ __forceinline__ int pmod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// fills and copies
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = val;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+__global__ void k_copy_i64(int64_t* __restrict__ dst, const int64_t* __restrict__ src, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: global positions -> (cell, offset); n_CR, J_CR deposit
+// ---------------------------------------------------------------------------
+
+template <int NDIM, typename PS, typename T>
+__global__ void k_init_convert(PS P, const double* __restrict__ x, const double* __restrict__ v,
+                               const double* __restrict__ m, const double* __restrict__ qm,
+                               const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
+                               int nb, int64_t N, uint32_t* err) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    int b = find_box(part_off, nb, j);
+    const BoxDev& bx = boxes[b];
+    int ic[3] = {0, 0, 0};
+    bool bad = false;
+    for (int d = 0; d < NDIM; ++d) {
+        double s = (x[d * N + j] - bx.x0[d]) / bx.dx[d];
+        double fl = floor(s);
+        if (!isfinite(s)) bad = true;
+        double off = (s - fl) - 0.5;
+        ic[d] = bad ? 0 : pmod((int)(long long)fl, bx.n[d]);
+        T o = (T)off;
+        if (o >= (T)0.5) {  // binary32 rounding can reach the upper edge
+            o = o - (T)1;
+            ic[d] = wrap_shift(ic[d], 1, bx.n[d]);
+        }
+        P.d[d][j] = o;
+    }
+    for (int d = 0; d < 3; ++d) {
+        double vd = v[d * N + j];
+        if (!isfinite(vd)) bad = true;
+        P.v[d][j] = (T)vd;
+    }
+    if (!isfinite(m[j]) || !isfinite(qm[j])) bad = true;
+    if (bad) latch(err, ERRBIT_NONFINITE);
+    P.cell[j] = pack_cell<NDIM>(ic[0], ic[1], ic[2]);
+    P.m[j] = m[j];
+    P.qm[j] = qm[j];
+    P.pid[j] = (int32_t)j;
+}
+
+// Deposits amount V over a 3^NDIM stencil straight into global int64 arrays.
+template <int NDIM>
+__device__ __forceinline__ void deposit_global(int64_t* dst, const BoxDev& bx, const int i[3],
+                                               const double wx[3], const double wy[3],
+                                               const double wz[3], double V) {
+    int64_t tot = quant1(V);
+    int64_t acc = 0;
+    const int zlo = NDIM == 3 ? 0 : 1, zhi = NDIM == 3 ? 2 : 1;
+    int64_t centre = 0;
+    for (int oz = zlo; oz <= zhi; ++oz)
+        for (int oy = 0; oy < 3; ++oy)
+            for (int ox = 0; ox < 3; ++ox) {
+                int cx = pmod(i[0] + ox - 1, bx.n[0]);
+                int cy = pmod(i[1] + oy - 1, bx.n[1]);
+                int cz = NDIM == 3 ? pmod(i[2] + oz - 1, bx.n[2]) : 0;
+                int64_t g = bx.cell_off + ((int64_t)cz * bx.n[1] + cy) * bx.n[0] + cx;
+                if (ox == 1 && oy == 1 && oz == 1) {
+                    centre = g;
+                    continue;
+                }
+                double wxy = wx[ox] * wy[oy];
+                double W = NDIM == 3 ? wxy * wz[oz] : wxy;
+                int64_t q = quant(W, V);
+                acc += q;
+                atomicAdd((unsigned long long*)&dst[g], (unsigned long long)q);
+            }
+    atomicAdd((unsigned long long*)&dst[centre], (unsigned long long)(tot - acc));
+}
+
+// n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
+// with global atomics; used once at initialisation.
+template <int NDIM>
+__global__ void k_deposit_nJ_global(PartF64 P, int64_t* __restrict__ nJ, int64_t NC,
+                                    const BoxDev* __restrict__ boxes,
+                                    const int64_t* __restrict__ part_off, int nb, int64_t N,
+                                    uint32_t* err) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+    int i[3];
+    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+    double wx[3], wy[3], wz[3] = {0.0, 1.0, 0.0};
+    tsc(P.d[0][j], wx);
+    tsc(P.d[1][j], wy);
+    if (NDIM == 3) tsc(P.d[2][j], wz);
+    double v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
+    Kin k = lorentz(v, bx.C, bx.C2, bx.iC);
+    double qmm = P.qm[j] * P.m[j];
+    double V[4] = {qmm * bx.S, (qmm * k.u[0]) * bx.S, (qmm * k.u[1]) * bx.S, (qmm * k.u[2]) * bx.S};
+    for (int c = 0; c < 4; ++c) {
+        if (!(fabs(V[c]) < kMaxAmount)) {
+            latch(err, ERRBIT_RANGE);
+            continue;
+        }
+        deposit_global<NDIM>(nJ + c * NC, bx, i, wx, wy, wz, V[c]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binning by tile of the half-step cell x^(n+1/2)
+// ---------------------------------------------------------------------------
+
+template <int NDIM>
+__device__ __forceinline__ uint32_t tile_of(const BoxDev& bx, const int3 T, int ix, int iy,
+                                            int iz) {
+    int tx = ix / T.x, ty = iy / T.y, tz = NDIM == 3 ? iz / T.z : 0;
+    return (uint32_t)(bx.tile_off + (tz * bx.nt[1] + ty) * bx.nt[0] + tx);
+}
+
+// Key = tile of the cell reached by a half drift with this call's dt; the
+// push repeats the same operations, so it finds the particle in that tile.
+template <int NDIM, typename PS>
+__global__ void k_rekey(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
+                        const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
+                        int nb, int64_t N, int3 T) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = j < N;
+    uint32_t k = 0;
+    if (act) {
+        const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+        int i[3];
+        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+        double v[3] = {(double)P.v[0][j], (double)P.v[1][j], (double)P.v[2][j]};
+        Kin kn = lorentz(v, bx.C, bx.C2, bx.iC);
+        for (int d = 0; d < NDIM; ++d) {
+            double dl = (double)P.d[d][j];
+            int s = drift1(dl, kn.u[d], bx.hdx[d]);
+            i[d] = wrap_shift(i[d], s, bx.n[d]);
+        }
+        k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+        key[j] = k;
+    }
+    wave_claim(count, k, act);
+}
+
+// Exclusive scan of tile counts and the work list: each tile's particles are
+// split into items of at most P particles.  One block of 1024 threads.
+__global__ void __launch_bounds__(1024)
+k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
+       uint32_t* __restrict__ cursor, const int32_t* __restrict__ tile_box,
+       WorkItem* __restrict__ items, uint32_t* __restrict__ n_items, int NT, int P) {
+    __shared__ uint32_t s_a[1024], s_b[1024];
+    const int t = threadIdx.x;
+    const int per = (NT + 1023) / 1024;
+    const int t0 = min(t * per, NT), t1 = min(t0 + per, NT);
+    uint32_t sum = 0, nit = 0;
+    for (int i = t0; i < t1; ++i) {
+        uint32_t c = count[i];
+        sum += c;
+        nit += (c + P - 1) / P;
+    }
+    s_a[t] = sum;
+    s_b[t] = nit;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t a = t >= off ? s_a[t - off] : 0u;
+        uint32_t b = t >= off ? s_b[t - off] : 0u;
+        __syncthreads();
+        s_a[t] += a;
+        s_b[t] += b;
+        __syncthreads();
+    }
+    uint32_t off = s_a[t] - sum;
+    uint32_t io = s_b[t] - nit;
+    for (int i = t0; i < t1; ++i) {
+        uint32_t c = count[i];
+        start[i] = off;
+        cursor[i] = off;
+        for (uint32_t k = 0; k < c; k += (uint32_t)P) {
+            WorkItem w;
+            w.tile = i;
+            w.begin = (int32_t)(off + k);
+            w.end = (int32_t)(off + min(k + (uint32_t)P, c));
+            w.box = tile_box[i];
+            items[io++] = w;
+        }
+        off += c;
+    }
+    if (t == 1023) {
+        start[NT] = s_a[1023];
+        *n_items = s_b[1023];
+    }
+}
+
+// Moves every particle to its slot in the tile-sorted order.
+template <int NDIM, typename PS>
+__global__ void k_scatter(PS A, PS Bo, const uint32_t* __restrict__ key,
+                          uint32_t* __restrict__ cursor, int64_t N) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = j < N;
+    uint32_t k = act ? key[j] : 0u;
+    uint32_t s = wave_claim(cursor, k, act);
+    if (!act) return;
+    Bo.cell[s] = A.cell[j];
+    for (int d = 0; d < NDIM; ++d) Bo.d[d][s] = A.d[d][j];
+    for (int d = 0; d < 3; ++d) Bo.v[d][s] = A.v[d][j];
+    Bo.m[s] = A.m[j];
+    Bo.qm[s] = A.qm[j];
+    Bo.pid[s] = A.pid[j];
+}
+
+// ---------------------------------------------------------------------------
+// cell-centred fields: E0 = -v_g x B and the CR-Hall correction (Sec. 2.1)
+// ---------------------------------------------------------------------------
+
+// Writes EB[cell] = (Ex, Ey, Ez, Bx, By, Bz) interleaved for the gather.
+template <typename TF>
+__global__ void k_fieldprep(TF* __restrict__ EB, const double* __restrict__ B,
+                            const double* __restrict__ vg, const double* __restrict__ rho,
+                            const int64_t* __restrict__ nJ, const BoxDev* __restrict__ boxes,
+                            const int64_t* __restrict__ cell_off, int nb, int64_t NC) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= NC) return;
+    const BoxDev& bx = boxes[find_box(cell_off, nb, c)];
+    double b0 = B[c], b1 = B[NC + c], b2 = B[2 * NC + c];
+    double g0 = vg[c], g1 = vg[NC + c], g2 = vg[2 * NC + c];
+    double e0[3];
+    e0[0] = -(g1 * b2 - g2 * b1);
+    e0[1] = -(g2 * b0 - g0 * b2);
+    e0[2] = -(g0 * b1 - g1 * b0);
+    double e[3] = {e0[0], e0[1], e0[2]};
+    if (bx.hall) {
+        double n = ((double)nJ[c] * bx.iS) / bx.dV;
+        double J0 = ((double)nJ[NC + c] * bx.iS) / bx.dV;
+        double J1 = ((double)nJ[2 * NC + c] * bx.iS) / bx.dV;
+        double J2 = ((double)nJ[3 * NC + c] * bx.iS) / bx.dV;
+        double ng = bx.qg * rho[c];
+        double R = n / (ng + n);
+        double jxb[3];
+        jxb[0] = J1 * b2 - J2 * b1;
+        jxb[1] = J2 * b0 - J0 * b2;
+        jxb[2] = J0 * b1 - J1 * b0;
+        for (int d = 0; d < 3; ++d) {
+            double F = (1.0 - R) * (n * e0[d] + jxb[d]);
+            e[d] = e0[d] - F / ng;
+        }
+    }
+    TF* o = EB + 6 * c;
+    o[0] = (TF)e[0];
+    o[1] = (TF)e[1];
+    o[2] = (TF)e[2];
+    o[3] = (TF)b0;
+    o[4] = (TF)b1;
+    o[5] = (TF)b2;
+}
+
+// ---------------------------------------------------------------------------
+// read-out in the original particle order
+// ---------------------------------------------------------------------------
+
+template <int NDIM, typename PS>
+__global__ void k_read_particles(PS P, double* __restrict__ x, double* __restrict__ v,
+                                 const BoxDev* __restrict__ boxes,
+                                 const int64_t* __restrict__ part_off, int nb, int64_t N) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+    int64_t p = P.pid[j];
+    int i[3];
+    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+    for (int d = 0; d < 3; ++d) {
+        double xd = 0.0;
+        if (d < NDIM) xd = bx.x0[d] + bx.dx[d] * (((double)i[d] + 0.5) + (double)P.d[d][j]);
+        x[d * N + p] = xd;
+        v[d * N + p] = (double)P.v[d][j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// arithmetic self-test
+// ---------------------------------------------------------------------------
+
+__global__ void k_selftest(const double* a, const double* b, const double* c, double* out,
+                           int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = __builtin_sqrt(a[i]);
+    out[n + i] = a[i] / b[i];
+    out[2 * n + i] = __builtin_fma(a[i], b[i], c[i]);
+    out[3 * n + i] = (double)(long long)__double_as_longlong(c[i]);
+}
+
+}  // namespace mhdpic

@@ -1,0 +1,699 @@
+// Host runtime and C ABI of the MHD-PIC cosmic-ray particle library.
+//
+// Per mhdpic_step call (fields fixed, dt per box):
+//   rekey -> scan -> scatter          bin particles by the tile of x^(n+1/2)
+//   per step:
+//     fieldprep                       cell-centred E (Sec. 2.1)
+//     push                            gather + Boris + deposits (App. A.2, A.3);
+//                                     also counts particles per next tile
+//     scan -> scatter (not after the last step)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mhdpic.h"
+#include "common.h"
+#include "kernels.h"
+#include "push_f64.h"
+#include "push_f32.h"
+
+using namespace mhdpic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(MHDPIC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kItemParticles = 4096;  // particles per push work item
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Tile shapes with compiled push kernels.
+struct TileShape {
+    int x, y, z;
+};
+
+bool tile_supported(int ndim, int prec, const TileShape& t) {
+    if (ndim == 2) {
+        return (t.x == 16 && t.y == 16) || (t.x == 32 && t.y == 16) || (t.x == 8 && t.y == 8) ||
+               (t.x == 32 && t.y == 32) || (t.x == 64 && t.y == 16);
+    }
+    return (t.x == 8 && t.y == 4 && t.z == 4) || (t.x == 8 && t.y == 8 && t.z == 4) ||
+           (t.x == 4 && t.y == 4 && t.z == 4) || (t.x == 8 && t.y == 8 && t.z == 8) ||
+           (t.x == 16 && t.y == 4 && t.z == 4);
+    (void)prec;
+}
+
+TileShape default_tile(int ndim, int prec) {
+    (void)prec;
+    if (ndim == 2) return {16, 16, 1};
+    return {8, 4, 4};
+}
+
+struct Layout {
+    // sizes
+    int64_t N = 0, NC = 0;
+    int32_t NT = 0, NW = 0;
+    // offsets into the workspace
+    size_t partA = 0, partB = 0, part_bytes = 0;
+    size_t key = 0, EB = 0, Dcorr = 0, nJ0 = 0, nJ1 = 0;
+    size_t count = 0, start = 0, cursor = 0, tile_box = 0, items = 0, n_items = 0, err = 0;
+    size_t boxes = 0, part_off = 0, cell_off = 0;
+    size_t total = 0;
+};
+
+}  // namespace
+
+struct mhdpic_ctx {
+    int ndim = 0, precision = 0, nb = 0;
+    TileShape tile{};
+    std::vector<mhdpic_box> boxes;
+    std::vector<BoxDev> bdev;
+    std::vector<int64_t> part_off, cell_off;
+    Layout L;
+    unsigned char* ws = nullptr;
+    int cur = 0;   // which particle buffer (0 = A, 1 = B) holds the state
+    int nj = 0;    // which nJ buffer is current
+    hipStream_t last_stream = nullptr;
+    uint32_t* err_host = nullptr;  // pinned copy of the error word
+    hipEvent_t err_event = nullptr;
+    bool err_pending = false;
+};
+
+namespace {
+
+int validate_boxes(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32_t precision,
+                   int& ndim, TileShape& tile) {
+    if (!boxes || nb < 1 || !np) return fail(MHDPIC_EINVAL, "boxes, n_boxes or n_particles invalid");
+    if (precision != MHDPIC_FP64 && precision != MHDPIC_FP32_MIXED)
+        return fail(MHDPIC_EINVAL, "precision must be MHDPIC_FP64 or MHDPIC_FP32_MIXED");
+    ndim = boxes[0].ndim;
+    if (ndim != 2 && ndim != 3) return fail(MHDPIC_EINVAL, "ndim must be 2 or 3");
+    tile = {boxes[0].tile[0], boxes[0].tile[1], ndim == 3 ? boxes[0].tile[2] : 1};
+    if (tile.x == 0 && tile.y == 0) tile = default_tile(ndim, precision);
+    if (!tile_supported(ndim, precision, tile))
+        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");
+    int64_t N = 0, NC = 0;
+    for (int b = 0; b < nb; ++b) {
+        const mhdpic_box& B = boxes[b];
+        if (B.ndim != ndim) return fail(MHDPIC_EINVAL, "all boxes must have the same ndim");
+        int tz = ndim == 3 ? B.tile[2] : 1;
+        bool same = (B.tile[0] == 0 && B.tile[1] == 0) ? (tile.x == default_tile(ndim, precision).x &&
+                                                           tile.y == default_tile(ndim, precision).y)
+                                                        : (B.tile[0] == tile.x && B.tile[1] == tile.y &&
+                                                           tz == tile.z);
+        if (!same) return fail(MHDPIC_EINVAL, "all boxes must use the same tile shape");
+        for (int d = 0; d < ndim; ++d) {
+            if (B.n[d] < 1) return fail(MHDPIC_EINVAL, "cell counts must be >= 1");
+            if (!(B.dx[d] > 0.0) || !std::isfinite(B.dx[d])) return fail(MHDPIC_EINVAL, "dx must be > 0");
+            if (!std::isfinite(B.x0[d])) return fail(MHDPIC_EINVAL, "x0 must be finite");
+        }
+        if (ndim == 2 && B.n[2] != 1) return fail(MHDPIC_EINVAL, "n[2] must be 1 in 2D");
+        if (ndim == 2 && (B.n[0] > 65536 || B.n[1] > 65536)) return fail(MHDPIC_ERANGE, "2D box too large");
+        if (ndim == 3 && (B.n[0] > 2048 || B.n[1] > 2048 || B.n[2] > 1024))
+            return fail(MHDPIC_ERANGE, "3D box too large");
+        if (!(B.C > 0.0) || !std::isfinite(B.C)) return fail(MHDPIC_EINVAL, "C must be > 0");
+        if (B.frac_bits < 0 || B.frac_bits > 60) return fail(MHDPIC_EINVAL, "frac_bits must be in 0..60");
+        if (B.max_move_cells < 1 || B.max_move_cells > 2) return fail(MHDPIC_EINVAL, "max_move_cells must be 1 or 2");
+        if (B.hall && !(B.qomc_gas != 0.0 && std::isfinite(B.qomc_gas)))
+            return fail(MHDPIC_EINVAL, "qomc_gas must be finite and nonzero with hall = 1");
+        if (np[b] < 0) return fail(MHDPIC_EINVAL, "negative particle count");
+        N += np[b];
+        NC += (int64_t)B.n[0] * B.n[1] * (ndim == 3 ? B.n[2] : 1);
+    }
+    if (N >= (int64_t)1 << 31) return fail(MHDPIC_ERANGE, "at most 2^31-1 particles");
+    if (NC >= (int64_t)1 << 31) return fail(MHDPIC_ERANGE, "at most 2^31-1 cells");
+    return MHDPIC_OK;
+}
+
+Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32_t precision,
+                   int ndim, const TileShape& tile) {
+    Layout L;
+    for (int b = 0; b < nb; ++b) {
+        const mhdpic_box& B = boxes[b];
+        L.N += np[b];
+        L.NC += (int64_t)B.n[0] * B.n[1] * (ndim == 3 ? B.n[2] : 1);
+        int ntx = (B.n[0] + tile.x - 1) / tile.x, nty = (B.n[1] + tile.y - 1) / tile.y;
+        int ntz = ndim == 3 ? (B.n[2] + tile.z - 1) / tile.z : 1;
+        L.NT += ntx * nty * ntz;
+    }
+    L.NW = L.NT + (int32_t)(L.N / kItemParticles) + 1;
+    const size_t N = (size_t)L.N, NC = (size_t)L.NC;
+    const size_t fsz = precision == MHDPIC_FP64 ? 8 : 4;
+    // cell, d[ndim], v[3], m, qm (fsz each), pid
+    L.part_bytes = align_up(N * 4) + (size_t)ndim * align_up(N * fsz) + 3 * align_up(N * fsz) +
+                   2 * align_up(N * fsz) + align_up(N * 4);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align_up(bytes);
+        return r;
+    };
+    L.partA = take(L.part_bytes);
+    L.partB = take(L.part_bytes);
+    L.key = take(N * 4);
+    L.EB = take(NC * 6 * fsz);
+    L.Dcorr = take(NC * 4 * 8);
+    L.nJ0 = take(NC * 4 * 8);
+    L.nJ1 = take(NC * 4 * 8);
+    L.count = take((size_t)L.NT * 4);
+    L.start = take((size_t)(L.NT + 1) * 4);
+    L.cursor = take((size_t)L.NT * 4);
+    L.tile_box = take((size_t)L.NT * 4);
+    L.items = take((size_t)L.NW * sizeof(WorkItem));
+    L.n_items = take(4);
+    L.err = take(4);
+    L.boxes = take((size_t)nb * sizeof(BoxDev));
+    L.part_off = take((size_t)(nb + 1) * 8);
+    L.cell_off = take((size_t)(nb + 1) * 8);
+    L.total = o;
+    return L;
+}
+
+template <typename PS, typename T>
+PS carve_particles(unsigned char* base, size_t N, int ndim) {
+    PS P{};
+    size_t o = 0;
+    P.cell = reinterpret_cast<uint32_t*>(base + o);
+    o += align_up(N * 4);
+    for (int d = 0; d < 3; ++d) {
+        if (d < ndim) {
+            P.d[d] = reinterpret_cast<T*>(base + o);
+            o += align_up(N * sizeof(T));
+        } else {
+            P.d[d] = nullptr;
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        P.v[d] = reinterpret_cast<T*>(base + o);
+        o += align_up(N * sizeof(T));
+    }
+    P.m = reinterpret_cast<T*>(base + o);
+    o += align_up(N * sizeof(T));
+    P.qm = reinterpret_cast<T*>(base + o);
+    o += align_up(N * sizeof(T));
+    P.pid = reinterpret_cast<int32_t*>(base + o);
+    return P;
+}
+
+template <typename PS, typename T>
+PS part(mhdpic_ctx* c, int which) {
+    size_t off = which == 0 ? c->L.partA : c->L.partB;
+    return carve_particles<PS, T>(c->ws + off, (size_t)c->L.N, c->ndim);
+}
+
+template <typename T>
+T* at(mhdpic_ctx* c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+void fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(n, 256), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, n, val);
+}
+
+void fill_i64(int64_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(n, 256), 8192);
+    hipLaunchKernelGGL(k_fill_i64, dim3(g), dim3(256), 0, s, p, n);
+}
+
+// Latched device error -> code.
+int code_of(uint32_t bits) {
+    if (bits & ERRBIT_NONFINITE) return MHDPIC_ENONFINITE;
+    if (bits & ERRBIT_RANGE) return MHDPIC_ERANGE;
+    if (bits & ERRBIT_STATE) return MHDPIC_ESTATE;
+    return MHDPIC_OK;
+}
+
+const char* msg_of(uint32_t bits) {
+    if (bits & ERRBIT_NONFINITE) return "device: a position or velocity is not finite";
+    if (bits & ERRBIT_RANGE) return "device: a deposit amount reached 2^51 quanta";
+    if (bits & ERRBIT_STATE) return "device: a particle was outside its tile";
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers, dispatched on (ndim, precision, tile)
+// ---------------------------------------------------------------------------
+
+template <int NDIM, typename PS, typename T>
+int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
+    const Layout& L = c->L;
+    const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
+    PS A = part<PS, T>(c, c->cur);
+    PS Bo = part<PS, T>(c, 1 - c->cur);
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const int64_t* po = at<int64_t>(c, L.part_off);
+    if (rekey) {
+        fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
+        if (L.N > 0) {
+            if constexpr (std::is_same<PS, PartF64>::value)
+                hipLaunchKernelGGL((k_rekey<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
+                                   at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), bd, po, c->nb, L.N, T3);
+            else
+                hipLaunchKernelGGL((k_rekey_f32<NDIM>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
+                                   at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), bd, po, c->nb, L.N, T3);
+        }
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
+                       at<uint32_t>(c, L.start), at<uint32_t>(c, L.cursor), at<int32_t>(c, L.tile_box),
+                       at<WorkItem>(c, L.items), at<uint32_t>(c, L.n_items), L.NT, kItemParticles);
+    if (L.N > 0)
+        hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A, Bo,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N);
+    c->cur = 1 - c->cur;
+    return MHDPIC_OK;
+}
+
+template <int NDIM, int TX, int TY, int TZ>
+int launch_push_f64_t(mhdpic_ctx* c, hipStream_t s) {
+    constexpr int BLOCK = 256;
+    using TL = Tiling<NDIM, TX, TY, TZ>;
+    const Layout& L = c->L;
+    PushArgs a;
+    a.P = part<PartF64, double>(c, c->cur);
+    a.key = at<uint32_t>(c, L.key);
+    a.count = at<uint32_t>(c, L.count);
+    a.EB = at<double>(c, L.EB);
+    a.Dcorr = at<int64_t>(c, L.Dcorr);
+    a.nJ = at<int64_t>(c, c->nj == 0 ? L.nJ1 : L.nJ0);  // next buffer
+    a.boxes = at<BoxDev>(c, L.boxes);
+    a.items = at<WorkItem>(c, L.items);
+    a.n_items = at<uint32_t>(c, L.n_items);
+    a.err = at<uint32_t>(c, L.err);
+    a.NC = L.NC;
+    size_t lds = TL::lds_bytes();
+    auto kern = k_push_f64<NDIM, TX, TY, TZ, BLOCK>;
+    if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    unsigned grid = (unsigned)((L.NW + 7) / 8 * 8);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    return MHDPIC_OK;
+}
+
+template <int NDIM, int TX, int TY, int TZ>
+int launch_push_f32_t(mhdpic_ctx* c, hipStream_t s) {
+    constexpr int BLOCK = 256;
+    using TL = Tiling32<NDIM, TX, TY, TZ>;
+    const Layout& L = c->L;
+    PushArgs32 a;
+    a.P = part<PartF32, float>(c, c->cur);
+    a.key = at<uint32_t>(c, L.key);
+    a.count = at<uint32_t>(c, L.count);
+    a.EB = at<float>(c, L.EB);
+    a.Dcorr = at<int64_t>(c, L.Dcorr);
+    a.nJ = at<int64_t>(c, c->nj == 0 ? L.nJ1 : L.nJ0);
+    a.boxes = at<BoxDev>(c, L.boxes);
+    a.items = at<WorkItem>(c, L.items);
+    a.n_items = at<uint32_t>(c, L.n_items);
+    a.err = at<uint32_t>(c, L.err);
+    a.NC = L.NC;
+    size_t lds = TL::lds_bytes();
+    auto kern = k_push_f32<NDIM, TX, TY, TZ, BLOCK>;
+    if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    unsigned grid = (unsigned)((L.NW + 7) / 8 * 8);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    return MHDPIC_OK;
+}
+
+template <int NDIM, int TX, int TY, int TZ>
+int launch_push_t(mhdpic_ctx* c, hipStream_t s) {
+    if (c->precision == MHDPIC_FP64) return launch_push_f64_t<NDIM, TX, TY, TZ>(c, s);
+    return launch_push_f32_t<NDIM, TX, TY, TZ>(c, s);
+}
+
+int launch_push(mhdpic_ctx* c, hipStream_t s) {
+    const TileShape& t = c->tile;
+    if (c->ndim == 2) {
+        if (t.x == 16 && t.y == 16) return launch_push_t<2, 16, 16, 1>(c, s);
+        if (t.x == 32 && t.y == 16) return launch_push_t<2, 32, 16, 1>(c, s);
+        if (t.x == 8 && t.y == 8) return launch_push_t<2, 8, 8, 1>(c, s);
+        if (t.x == 32 && t.y == 32) return launch_push_t<2, 32, 32, 1>(c, s);
+        if (t.x == 64 && t.y == 16) return launch_push_t<2, 64, 16, 1>(c, s);
+    } else {
+        if (t.x == 8 && t.y == 4 && t.z == 4) return launch_push_t<3, 8, 4, 4>(c, s);
+        if (t.x == 8 && t.y == 8 && t.z == 4) return launch_push_t<3, 8, 8, 4>(c, s);
+        if (t.x == 4 && t.y == 4 && t.z == 4) return launch_push_t<3, 4, 4, 4>(c, s);
+        if (t.x == 8 && t.y == 8 && t.z == 8) return launch_push_t<3, 8, 8, 8>(c, s);
+        if (t.x == 16 && t.y == 4 && t.z == 4) return launch_push_t<3, 16, 4, 4>(c, s);
+    }
+    return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");
+}
+
+int launch_bin_any(mhdpic_ctx* c, hipStream_t s, bool rekey) {
+    if (c->precision == MHDPIC_FP64) {
+        if (c->ndim == 2) return launch_bin<2, PartF64, double>(c, s, rekey);
+        return launch_bin<3, PartF64, double>(c, s, rekey);
+    }
+    if (c->ndim == 2) return launch_bin<2, PartF32, float>(c, s, rekey);
+    return launch_bin<3, PartF32, float>(c, s, rekey);
+}
+
+int launch_fieldprep(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                     hipStream_t s) {
+    const Layout& L = c->L;
+    const int64_t* nJcur = at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1);
+    if (c->precision == MHDPIC_FP64)
+        hipLaunchKernelGGL(k_fieldprep<double>, dim3(grid_for(L.NC, 256)), dim3(256), 0, s,
+                           at<double>(c, L.EB), B, vg, rho, nJcur, at<BoxDev>(c, L.boxes),
+                           at<int64_t>(c, L.cell_off), c->nb, L.NC);
+    else
+        hipLaunchKernelGGL(k_fieldprep<float>, dim3(grid_for(L.NC, 256)), dim3(256), 0, s,
+                           at<float>(c, L.EB), B, vg, rho, nJcur, at<BoxDev>(c, L.boxes),
+                           at<int64_t>(c, L.cell_off), c->nb, L.NC);
+    return MHDPIC_OK;
+}
+
+// Pick up a device error latched by earlier work, without waiting for it.
+int poll_error(mhdpic_ctx* c) {
+    if (!c->err_pending) return MHDPIC_OK;
+    hipError_t q = hipEventQuery(c->err_event);
+    if (q == hipErrorNotReady) return MHDPIC_OK;
+    c->err_pending = false;
+    if (q != hipSuccess) return fail(MHDPIC_EDEVICE, hipGetErrorString(q));
+    uint32_t bits = *c->err_host;
+    if (bits) return fail(code_of(bits), msg_of(bits));
+    return MHDPIC_OK;
+}
+
+int post_error_copy(mhdpic_ctx* c, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(c->err_host, at<uint32_t>(c, c->L.err), 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->err_event, s));
+    c->err_pending = true;
+    return MHDPIC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* mhdpic_last_error(void) { return g_last_error.c_str(); }
+
+int mhdpic_workspace_size(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                          int32_t precision, size_t* bytes) {
+    if (!bytes) return fail(MHDPIC_EINVAL, "bytes is NULL");
+    int ndim;
+    TileShape tile;
+    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
+    if (rc) return rc;
+    *bytes = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile).total;
+    return MHDPIC_OK;
+}
+
+int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                int32_t precision, const double* x, const double* v, const double* m,
+                const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
+                mhdpic_ctx** out) {
+    if (!out) return fail(MHDPIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndim;
+    TileShape tile;
+    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
+    if (rc) return rc;
+    Layout L = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile);
+    if (!workspace) return fail(MHDPIC_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace) % kAlign) return fail(MHDPIC_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(MHDPIC_ENOMEM, "workspace too small");
+    if (L.N > 0 && (!x || !v || !m || !qm)) return fail(MHDPIC_EINVAL, "particle arrays are NULL");
+
+    mhdpic_ctx* c = new mhdpic_ctx();
+    c->ndim = ndim;
+    c->precision = precision;
+    c->nb = n_boxes;
+    c->tile = tile;
+    c->L = L;
+    c->ws = static_cast<unsigned char*>(workspace);
+    c->boxes.assign(boxes, boxes + n_boxes);
+    c->part_off.assign(n_boxes + 1, 0);
+    c->cell_off.assign(n_boxes + 1, 0);
+    std::vector<int32_t> tile_box;
+    int32_t toff = 0;
+    for (int b = 0; b < n_boxes; ++b) {
+        const mhdpic_box& B = boxes[b];
+        BoxDev d{};
+        for (int k = 0; k < 3; ++k) {
+            d.n[k] = (k < ndim) ? B.n[k] : 1;
+            d.dx[k] = (k < ndim) ? B.dx[k] : 1.0;
+            d.x0[k] = (k < ndim) ? B.x0[k] : 0.0;
+        }
+        int T[3] = {tile.x, tile.y, ndim == 3 ? tile.z : 1};
+        for (int k = 0; k < 3; ++k) d.nt[k] = (d.n[k] + T[k] - 1) / T[k];
+        d.tile_off = toff;
+        int ntiles = d.nt[0] * d.nt[1] * d.nt[2];
+        for (int t = 0; t < ntiles; ++t) tile_box.push_back(b);
+        toff += ntiles;
+        d.hall = B.hall;
+        d.cell_off = c->cell_off[b];
+        d.part_off = c->part_off[b];
+        d.part_n = n_particles[b];
+        c->part_off[b + 1] = c->part_off[b] + n_particles[b];
+        c->cell_off[b + 1] = c->cell_off[b] + (int64_t)d.n[0] * d.n[1] * d.n[2];
+        d.C = B.C;
+        d.C2 = B.C * B.C;
+        d.iC = 1.0 / B.C;
+        d.qg = B.qomc_gas;
+        d.S = std::ldexp(1.0, B.frac_bits);
+        d.iS = std::ldexp(1.0, -B.frac_bits);
+        d.dV = B.dx[0] * B.dx[1];
+        if (ndim == 3) d.dV = d.dV * B.dx[2];
+        d.dt = d.hdt = 0.0;
+        d.hdx[0] = d.hdx[1] = d.hdx[2] = 0.0;
+        c->bdev.push_back(d);
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    auto cleanup = [&](int code) {
+        if (c->err_host) (void)hipHostFree(c->err_host);
+        if (c->err_event) (void)hipEventDestroy(c->err_event);
+        delete c;
+        return code;
+    };
+    if (hipHostMalloc((void**)&c->err_host, 4, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(MHDPIC_EDEVICE, "hipHostMalloc failed"));
+    *c->err_host = 0;
+    if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(MHDPIC_EDEVICE, "hipEventCreate failed"));
+
+#define INIT_TRY(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return cleanup(fail(MHDPIC_EDEVICE, std::string(#expr) + ": " + \
+                                                                      hipGetErrorString(e_))); \
+    } while (0)
+
+    INIT_TRY(hipMemcpyAsync(c->ws + L.boxes, c->bdev.data(), sizeof(BoxDev) * n_boxes,
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(c->ws + L.part_off, c->part_off.data(), 8 * (n_boxes + 1),
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(c->ws + L.cell_off, c->cell_off.data(), 8 * (n_boxes + 1),
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipMemcpyAsync(c->ws + L.tile_box, tile_box.data(), 4 * tile_box.size(),
+                            hipMemcpyHostToDevice, s));
+    INIT_TRY(hipStreamSynchronize(s));
+    fill_u32(at<uint32_t>(c, L.err), 1, 0u, s);
+    fill_i64(at<int64_t>(c, L.Dcorr), 4 * L.NC, s);
+    fill_i64(at<int64_t>(c, L.nJ0), 4 * L.NC, s);
+    c->cur = 0;
+    c->nj = 0;
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const int64_t* po = at<int64_t>(c, L.part_off);
+    if (L.N > 0) {
+        if (precision == MHDPIC_FP64) {
+            PartF64 P = part<PartF64, double>(c, 0);
+            if (ndim == 2)
+                hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            else
+                hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            if (ndim == 2)
+                hipLaunchKernelGGL(k_deposit_nJ_global<2>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            else
+                hipLaunchKernelGGL(k_deposit_nJ_global<3>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+        } else {
+            PartF32 P = part<PartF32, float>(c, 0);
+            if (ndim == 2)
+                hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            else
+                hipLaunchKernelGGL((k_init_convert<3, PartF32, float>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            if (ndim == 2)
+                hipLaunchKernelGGL(k_deposit_nJ_global_f32<2>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            else
+                hipLaunchKernelGGL(k_deposit_nJ_global_f32<3>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+        }
+    }
+    INIT_TRY(hipGetLastError());
+    uint32_t bits = 0;
+    INIT_TRY(hipMemcpyAsync(&bits, c->ws + L.err, 4, hipMemcpyDeviceToHost, s));
+    INIT_TRY(hipStreamSynchronize(s));
+    if (bits) {
+        int code = code_of(bits);
+        std::string msg = msg_of(bits);
+        return cleanup(fail(code, msg));
+    }
+#undef INIT_TRY
+    *out = c;
+    return MHDPIC_OK;
+}
+
+int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                const double* dt, int32_t n_steps, void* hip_stream) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    if (!dt || n_steps < 0) return fail(MHDPIC_EINVAL, "dt is NULL or n_steps < 0");
+    if (c->L.NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
+    bool any_hall = false;
+    for (auto& b : c->boxes) any_hall |= b.hall != 0;
+    if (any_hall && !rho) return fail(MHDPIC_EINVAL, "rho is NULL with hall = 1");
+    int rc = poll_error(c);
+    if (rc) return rc;
+    for (int b = 0; b < c->nb; ++b) {
+        const mhdpic_box& bx = c->boxes[b];
+        if (!std::isfinite(dt[b])) return fail(MHDPIC_EINVAL, "dt must be finite");
+        for (int d = 0; d < c->ndim; ++d) {
+            double cells = bx.C * std::fabs(dt[b]) / bx.dx[d];
+            if (!(cells <= bx.max_move_cells * (1.0 - 1e-12)))
+                return fail(MHDPIC_ERANGE, "C*|dt|/dx exceeds max_move_cells");
+        }
+    }
+    if (n_steps == 0) return MHDPIC_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    for (int b = 0; b < c->nb; ++b) {
+        BoxDev& d = c->bdev[b];
+        d.dt = dt[b];
+        d.hdt = 0.5 * dt[b];
+        for (int k = 0; k < 3; ++k) d.hdx[k] = k < c->ndim ? d.hdt / c->boxes[b].dx[k] : 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
+                           hipMemcpyHostToDevice, s));
+    if (!rho) rho = B;  // never read without the Hall term
+    rc = launch_bin_any(c, s, true);
+    if (rc) return rc;
+    for (int st = 0; st < n_steps; ++st) {
+        rc = launch_fieldprep(c, B, vg, rho, s);
+        if (rc) return rc;
+        int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
+        fill_i64(next, 4 * c->L.NC, s);
+        fill_u32(at<uint32_t>(c, c->L.count), c->L.NT, 0u, s);
+        rc = launch_push(c, s);
+        if (rc) return rc;
+        c->nj = 1 - c->nj;
+        if (st + 1 < n_steps) {
+            rc = launch_bin_any(c, s, false);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return post_error_copy(c, s);
+}
+
+int mhdpic_deposit_read(mhdpic_ctx* c, int64_t* out, int32_t reset_accumulated, void* hip_stream) {
+    if (!c || !out) return fail(MHDPIC_EINVAL, "ctx or out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    const int64_t NC = c->L.NC;
+    const int64_t* nJ = at<int64_t>(c, c->nj == 0 ? c->L.nJ0 : c->L.nJ1);
+    HIP_TRY(hipMemcpyAsync(out, nJ, 4 * NC * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(out + 4 * NC, at<int64_t>(c, c->L.Dcorr), 4 * NC * 8,
+                           hipMemcpyDeviceToDevice, s));
+    if (reset_accumulated) fill_i64(at<int64_t>(c, c->L.Dcorr), 4 * NC, s);
+    HIP_TRY(hipGetLastError());
+    return MHDPIC_OK;
+}
+
+int mhdpic_particles_read(mhdpic_ctx* c, double* x, double* v, void* hip_stream) {
+    if (!c || !x || !v) return fail(MHDPIC_EINVAL, "ctx, x or v is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    const Layout& L = c->L;
+    if (L.N == 0) return MHDPIC_OK;
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const int64_t* po = at<int64_t>(c, L.part_off);
+    if (c->precision == MHDPIC_FP64) {
+        PartF64 P = part<PartF64, double>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_read_particles<2, PartF64>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+        else
+            hipLaunchKernelGGL((k_read_particles<3, PartF64>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+    } else {
+        PartF32 P = part<PartF32, float>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_read_particles<2, PartF32>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+        else
+            hipLaunchKernelGGL((k_read_particles<3, PartF32>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+    }
+    HIP_TRY(hipGetLastError());
+    return MHDPIC_OK;
+}
+
+int mhdpic_check(mhdpic_ctx* c, void* hip_stream) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(c->err_host, at<uint32_t>(c, c->L.err), 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    c->err_pending = false;
+    uint32_t bits = *c->err_host;
+    fill_u32(at<uint32_t>(c, c->L.err), 1, 0u, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bits) return fail(code_of(bits), msg_of(bits));
+    return MHDPIC_OK;
+}
+
+int mhdpic_destroy(mhdpic_ctx* c) {
+    if (!c) return MHDPIC_OK;
+    if (c->err_event) {
+        (void)hipEventSynchronize(c->err_event);
+        (void)hipEventDestroy(c->err_event);
+    }
+    if (c->err_host) (void)hipHostFree(c->err_host);
+    delete c;
+    return MHDPIC_OK;
+}
+
+int mhdpic_selftest_arith(const double* a, const double* b, const double* cc, double* out,
+                          int64_t n, void* hip_stream) {
+    if (n <= 0) return MHDPIC_OK;
+    if (!a || !b || !cc || !out) return fail(MHDPIC_EINVAL, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(k_selftest, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, cc, out, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MHDPIC_OK;
+}
+
+}  // extern "C"

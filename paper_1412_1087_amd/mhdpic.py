@@ -1,0 +1,212 @@
+"""Thin ctypes binding of ``libmhdpic.so`` (the C ABI in ``include/mhdpic.h``).
+
+Argument marshalling only: every step of the particle update runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.  If
+the library has not been built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhdpic.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, FP32_MIXED = 0, 1
+
+EXPORTED = [
+    "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
+    "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
+    "mhdpic_selftest_arith",
+]
+
+
+class MhdpicBox(ct.Structure):
+    _fields_ = [("ndim", ct.c_int32), ("n", ct.c_int32 * 3), ("dx", ct.c_double * 3),
+                ("x0", ct.c_double * 3), ("C", ct.c_double), ("qomc_gas", ct.c_double),
+                ("hall", ct.c_int32), ("frac_bits", ct.c_int32), ("max_move_cells", ct.c_int32),
+                ("tile", ct.c_int32 * 3)]
+
+
+class MhdpicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mhdpic error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1412_1087_amd/build.py")
+        L = ct.CDLL(LIB_PATH)
+        vp, sz = ct.c_void_p, ct.c_size_t
+        L.mhdpic_workspace_size.restype = ct.c_int
+        L.mhdpic_workspace_size.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32,
+                                            ct.POINTER(ct.c_int64), ct.c_int32, ct.POINTER(sz)]
+        L.mhdpic_init.restype = ct.c_int
+        L.mhdpic_init.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32, ct.POINTER(ct.c_int64),
+                                  ct.c_int32, vp, vp, vp, vp, vp, sz, vp, ct.POINTER(vp)]
+        L.mhdpic_step.restype = ct.c_int
+        L.mhdpic_step.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32, vp]
+        L.mhdpic_deposit_read.restype = ct.c_int
+        L.mhdpic_deposit_read.argtypes = [vp, vp, ct.c_int32, vp]
+        L.mhdpic_particles_read.restype = ct.c_int
+        L.mhdpic_particles_read.argtypes = [vp, vp, vp, vp]
+        L.mhdpic_check.restype = ct.c_int
+        L.mhdpic_check.argtypes = [vp, vp]
+        L.mhdpic_destroy.restype = ct.c_int
+        L.mhdpic_destroy.argtypes = [vp]
+        L.mhdpic_last_error.restype = ct.c_char_p
+        L.mhdpic_last_error.argtypes = []
+        L.mhdpic_selftest_arith.restype = ct.c_int
+        L.mhdpic_selftest_arith.argtypes = [vp, vp, vp, vp, ct.c_int64, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise MhdpicError(rc, lib().mhdpic_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Box:
+    """Host description of one periodic box (mirrors ``mhdpic_box``)."""
+    ndim: int
+    n: Sequence[int]
+    dx: Sequence[float] = (1.0, 1.0, 1.0)
+    x0: Sequence[float] = (0.0, 0.0, 0.0)
+    C: float = 20.0
+    qomc_gas: float = 1.0
+    hall: int = 0
+    frac_bits: int = 40
+    max_move_cells: int = 2
+    tile: Sequence[int] = field(default_factory=lambda: (0, 0, 0))
+
+    def c_struct(self) -> MhdpicBox:
+        n = list(self.n) + [1] * (3 - len(self.n))
+        if self.ndim == 2:
+            n[2] = 1
+        b = MhdpicBox()
+        b.ndim = self.ndim
+        b.n = (ct.c_int32 * 3)(*n)
+        b.dx = (ct.c_double * 3)(*[float(a) for a in self.dx])
+        b.x0 = (ct.c_double * 3)(*[float(a) for a in self.x0])
+        b.C = float(self.C)
+        b.qomc_gas = float(self.qomc_gas)
+        b.hall = int(self.hall)
+        b.frac_bits = int(self.frac_bits)
+        b.max_move_cells = int(self.max_move_cells)
+        t = list(self.tile) + [0] * (3 - len(self.tile))
+        b.tile = (ct.c_int32 * 3)(*t)
+        return b
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.n[0] * self.n[1] * (self.n[2] if self.ndim == 3 else 1))
+
+
+def _boxes_array(boxes: Sequence[Box]):
+    arr = (MhdpicBox * len(boxes))()
+    for i, b in enumerate(boxes):
+        arr[i] = b.c_struct()
+    return arr
+
+
+def workspace_size(boxes: Sequence[Box], n_particles: Sequence[int], precision: int = FP64) -> int:
+    arr = _boxes_array(boxes)
+    npart = (ct.c_int64 * len(boxes))(*[int(a) for a in n_particles])
+    out = ct.c_size_t()
+    _check(lib().mhdpic_workspace_size(arr, len(boxes), npart, int(precision), ct.byref(out)))
+    return int(out.value)
+
+
+class Context:
+    """A set of boxes and their CR particles resident on one GPU."""
+
+    def __init__(self, boxes: Sequence[Box], n_particles: Sequence[int], x: torch.Tensor,
+                 v: torch.Tensor, m: torch.Tensor, qm: torch.Tensor, precision: int = FP64,
+                 stream=None):
+        self.boxes = list(boxes)
+        self.n_particles = [int(a) for a in n_particles]
+        self.N = sum(self.n_particles)
+        self.n_cells = sum(b.n_cells for b in self.boxes)
+        self.precision = precision
+        dev = x.device
+        for t in (x, v, m, qm):
+            assert t.dtype == torch.float64 and t.device == dev
+        nbytes = workspace_size(self.boxes, self.n_particles, precision)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        self._arr = _boxes_array(self.boxes)
+        npart = (ct.c_int64 * len(self.boxes))(*self.n_particles)
+        h = ct.c_void_p()
+        _check(lib().mhdpic_init(self._arr, len(self.boxes), npart, int(precision), _ptr(x), _ptr(v),
+                                 _ptr(m), _ptr(qm), _ptr(self.workspace), nbytes, _stream(stream),
+                                 ct.byref(h)))
+        self._h = h
+        self.device = dev
+
+    def step(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor | None, dt, n_steps: int = 1,
+             stream=None):
+        if isinstance(dt, (int, float)):
+            dt = [float(dt)] * len(self.boxes)
+        dts = (ct.c_double * len(self.boxes))(*[float(a) for a in dt])
+        _check(lib().mhdpic_step(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                 _stream(stream)))
+
+    def deposit_read(self, reset_accumulated: bool = False, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((8, self.n_cells), dtype=torch.int64, device=self.device)
+        _check(lib().mhdpic_deposit_read(self._h, _ptr(out), int(bool(reset_accumulated)),
+                                         _stream(stream)))
+        return out
+
+    def particles_read(self, stream=None):
+        x = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        v = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        _check(lib().mhdpic_particles_read(self._h, _ptr(x), _ptr(v), _stream(stream)))
+        return x, v
+
+    def check(self, stream=None):
+        _check(lib().mhdpic_check(self._h, _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mhdpic_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def selftest_arith(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:
+    n = a.numel()
+    out = torch.empty((4, n), dtype=torch.float64, device=a.device)
+    _check(lib().mhdpic_selftest_arith(_ptr(a), _ptr(b), _ptr(c), _ptr(out), n, _stream(stream)))
+    return out

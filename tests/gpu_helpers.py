@@ -1,0 +1,74 @@
+"""Helpers shared by the GPU tests: run one workload through the HIP library
+(via the C ABI binding) and through the oracle, from the same input bits."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_1412_1087_amd import workloads as W
+
+
+def oracle_box(spec: W.BoxSpec) -> O.Box:
+    return O.Box(ndim=spec.ndim, n=tuple(spec.n), dx=tuple(spec.dx), x0=tuple(spec.x0), C=spec.C,
+                 qomc_gas=spec.qomc_gas, hall=spec.hall, frac_bits=spec.frac_bits,
+                 max_move_cells=spec.max_move_cells)
+
+
+def gpu_box(spec: W.BoxSpec, tile=(0, 0, 0)):
+    from paper_1412_1087_amd import mhdpic as M
+    return M.Box(ndim=spec.ndim, n=tuple(spec.n), dx=tuple(spec.dx), x0=tuple(spec.x0), C=spec.C,
+                 qomc_gas=spec.qomc_gas, hall=spec.hall, frac_bits=spec.frac_bits,
+                 max_move_cells=spec.max_move_cells, tile=tuple(tile))
+
+
+def to_dev(a: np.ndarray, dev="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+class GpuRun:
+    """One or more workloads as the boxes of one GPU context."""
+
+    def __init__(self, wls, tile=(0, 0, 0), precision=0):
+        import torch
+        from paper_1412_1087_amd import mhdpic as M
+        if not isinstance(wls, (list, tuple)):
+            wls = [wls]
+        self.wls = list(wls)
+        self.boxes = [gpu_box(w.box, tile) for w in self.wls]
+        x = np.concatenate([w.x for w in self.wls], axis=1)
+        v = np.concatenate([w.v for w in self.wls], axis=1)
+        m = np.concatenate([w.m for w in self.wls])
+        qm = np.concatenate([w.qm for w in self.wls])
+        self.B = to_dev(np.concatenate([w.B for w in self.wls], axis=1))
+        self.vg = to_dev(np.concatenate([w.vg for w in self.wls], axis=1))
+        self.rho = to_dev(np.concatenate([w.rho for w in self.wls]))
+        self.ctx = M.Context(self.boxes, [w.N for w in self.wls], to_dev(x), to_dev(v), to_dev(m),
+                             to_dev(qm), precision=precision)
+        self.cell_off = np.cumsum([0] + [w.box.n_cells for w in self.wls])
+        self.part_off = np.cumsum([0] + [w.N for w in self.wls])
+        torch.cuda.synchronize()
+
+    def step(self, n_steps=1, dts=None):
+        import torch
+        if dts is None:
+            dts = [w.dt for w in self.wls]
+        self.ctx.step(self.B, self.vg, self.rho, dts, n_steps)
+        torch.cuda.synchronize()
+
+    def deposits(self):
+        import torch
+        D = self.ctx.deposit_read().cpu().numpy()
+        torch.cuda.synchronize()
+        return [D[:, self.cell_off[b]:self.cell_off[b + 1]] for b in range(len(self.wls))]
+
+    def particles(self):
+        x, v = self.ctx.particles_read()
+        x = x.cpu().numpy()
+        v = v.cpu().numpy()
+        return [(x[:, self.part_off[b]:self.part_off[b + 1]], v[:, self.part_off[b]:self.part_off[b + 1]])
+                for b in range(len(self.wls))]
+
+
+def oracle_run(wl: W.Workload) -> O.System:
+    return O.System(oracle_box(wl.box), wl.x, wl.v, wl.m, wl.qm)
