@@ -140,6 +140,16 @@ int mhdpic_destroy(mhdpic_ctx* ctx);
 /* Message for the last non-OK code returned on the calling thread. */
 const char* mhdpic_last_error(void);
 
+/* Per-phase kernel timing with HIP events recorded on the launch stream.
+ * mhdpic_timing_enable(ctx, 1) starts recording an event pair around every
+ * later phase launch of mhdpic_step; (ctx, 0) stops.  mhdpic_timing_read waits
+ * for the recorded events, writes the summed milliseconds and the number of
+ * launches of each phase (ms[4], launches[4]: 0 = binning (rekey, scan,
+ * scatter), 1 = cell-centred field preparation, 2 = fused gather/push/deposit,
+ * 3 = buffer clears) and clears the record. */
+int mhdpic_timing_enable(mhdpic_ctx* ctx, int32_t enable);
+int mhdpic_timing_read(mhdpic_ctx* ctx, double* ms, int64_t* launches);
+
 /* Arithmetic self-test: out[0][i] = sqrt(a[i]), out[1][i] = a[i]/b[i],
  * out[2][i] = fma(a[i], b[i], c[i]), out[3][i] = (double)(int64)bits of c[i]
  * reinterpreted, computed by the device with the rounding the step kernels

@@ -15,14 +15,14 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, SRC]
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=HERE)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -115,3 +115,118 @@ __device__ __forceinline__ int64_t quant1(double V) {
 }
 
 }  // namespace mhdpic
+
+namespace mhdpic {
+
+// ---------------------------------------------------------------------------
+// Precision form: binary32 offsets, velocities, fields and weights; the
+// Lorentz factor, u (rounded to binary32 afterwards) and E_k in binary64.
+// ---------------------------------------------------------------------------
+
+struct Kin32 {
+    float u[3];
+    double ek;
+};
+
+__device__ __forceinline__ Kin32 lorentz32(const float v[3], double C, double C2, double iC) {
+    Kin32 k;
+    double v0 = v[0], v1 = v[1], v2 = v[2];
+    double s = dot3(v0, v1, v2, v0, v1, v2);
+    double r = __builtin_sqrt(C2 + s);
+    double g = r * iC;
+    double ig = C / r;
+    k.u[0] = (float)(v0 * ig);
+    k.u[1] = (float)(v1 * ig);
+    k.u[2] = (float)(v2 * ig);
+    k.ek = s / (g + 1.0);
+    return k;
+}
+
+__device__ __forceinline__ int drift1f(float& d, float u, float hdx) {
+    d = d + u * hdx;
+    if (d >= 0.5f) {
+        d = d - 1.0f;
+        return 1;
+    }
+    if (d < -0.5f) {
+        d = d + 1.0f;
+        return -1;
+    }
+    return 0;
+}
+
+__device__ __forceinline__ void tscf(float d, float w[3]) {
+    float a = 0.5f - d;
+    float b = 0.5f + d;
+    w[0] = 0.5f * (a * a);
+    w[1] = 0.75f - d * d;
+    w[2] = 0.5f * (b * b);
+}
+
+// Policies used by the kernels that exist in both precisions.
+struct F64Pol {
+    using R = double;
+    using Part = PartF64;
+    struct K {
+        double u[3];
+        double ek;
+    };
+    __device__ static __forceinline__ K kin(const double v[3], double C, double C2, double iC) {
+        Kin k = lorentz(v, C, C2, iC);
+        return K{{k.u[0], k.u[1], k.u[2]}, k.ek};
+    }
+    __device__ static __forceinline__ double hdx(double h) { return h; }
+    __device__ static __forceinline__ int drift(double& d, double u, double h) { return drift1(d, u, h); }
+    __device__ static __forceinline__ void weights(double d, double w[3]) { tsc(d, w); }
+    __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    __device__ static __forceinline__ void clean(double E[3], const double B[3]) { clean_parallel(E, B); }
+    __device__ static __forceinline__ void push(const double v[3], const double E[3], const double B[3],
+                                                double hq, double C, double C2, double vn[3]) {
+        boris(v, E, B, hq, C, C2, vn);
+    }
+};
+
+struct F32Pol {
+    using R = float;
+    using Part = PartF32;
+    using K = Kin32;
+    __device__ static __forceinline__ K kin(const float v[3], double C, double C2, double iC) {
+        return lorentz32(v, C, C2, iC);
+    }
+    __device__ static __forceinline__ float hdx(double h) { return (float)h; }
+    __device__ static __forceinline__ int drift(float& d, float u, float h) { return drift1f(d, u, h); }
+    __device__ static __forceinline__ void weights(float d, float w[3]) { tscf(d, w); }
+    __device__ static __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    __device__ static __forceinline__ void clean(float E[3], const float B[3]) {
+        float eb = (E[0] * B[0] + E[1] * B[1]) + E[2] * B[2];
+        float bb = (B[0] * B[0] + B[1] * B[1]) + B[2] * B[2];
+        if (bb > 0.0f) {
+            float f = eb / bb;
+            E[0] = E[0] - f * B[0];
+            E[1] = E[1] - f * B[1];
+            E[2] = E[2] - f * B[2];
+        }
+    }
+    // binary32 kick and rotation; 1/gamma of v0 in binary64
+    __device__ static __forceinline__ void push(const float v[3], const float E[3], const float B[3],
+                                                double hqd, double C, double C2, float vn[3]) {
+        const float hq = (float)hqd;
+        float he0 = hq * E[0], he1 = hq * E[1], he2 = hq * E[2];
+        float w0 = v[0] + he0, w1 = v[1] + he1, w2 = v[2] + he2;
+        double wd0 = w0, wd1 = w1, wd2 = w2;
+        double rw = __builtin_sqrt(C2 + dot3(wd0, wd1, wd2, wd0, wd1, wd2));
+        float fr = (float)(hqd * (C / rw));
+        float t0 = fr * B[0], t1 = fr * B[1], t2 = fr * B[2];
+        float p0 = w0 + (w1 * t2 - w2 * t1);
+        float p1 = w1 + (w2 * t0 - w0 * t2);
+        float p2 = w2 + (w0 * t1 - w1 * t0);
+        float tt = (t0 * t0 + t1 * t1) + t2 * t2;
+        float c2 = 2.0f / (1.0f + tt);
+        float q0 = c2 * p0, q1 = c2 * p1, q2 = c2 * p2;
+        vn[0] = (w0 + (q1 * t2 - q2 * t1)) + he0;
+        vn[1] = (w1 + (q2 * t0 - q0 * t2)) + he1;
+        vn[2] = (w2 + (q0 * t1 - q1 * t0)) + he2;
+    }
+};
+
+}  // namespace mhdpic

@@ -1,0 +1,253 @@
+// Binning of particles by the tile of their half-step cell, without global
+// atomics on shared counters.
+//
+// Between steps a particle moves at most one tile in each dimension (tiles
+// are at least two cells wide and a step moves at most two cells), so each
+// particle's next tile is given by a direction code relative to the tile of
+// the work item that processed it: code = (cz*3 + cy)*3 + cx with c = 0, 1, 2
+// for -1, 0, +1 tiles (2D: cy*3 + cx).  A work item counts its particles per
+// code in LDS and stores the counts; one scan block turns all counts into the
+// destination offset of every (item, code) group and into the next work list;
+// the scatter then moves each particle to its group's offset plus a rank taken
+// from an LDS counter.  No counter is shared between blocks.
+#pragma once
+#include "kernels.h"
+#include "push.h"
+
+namespace mhdpic {
+
+// Cell of the half step x^(n+1/2) = x^(n) + u dt/2, with exactly the
+// operations of the step kernel of the precision form.
+template <class Pol, int NDIM>
+__device__ __forceinline__ void half_step_cell(const typename Pol::Part& P, int j, const BoxDev& bx,
+                                               int i[3]) {
+    using R = typename Pol::R;
+    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+    R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
+    typename Pol::K kn = Pol::kin(v, bx.C, bx.C2, bx.iC);
+    for (int d = 0; d < NDIM; ++d) {
+        R dl = P.d[d][j];
+        i[d] = wrap_shift(i[d], Pol::drift(dl, kn.u[d], Pol::hdx(bx.hdx[d])), bx.n[d]);
+    }
+}
+
+// Codes (and bank residues) for this call's dt; the push computes them for
+// the later steps of the call.
+template <class Pol, int NDIM>
+__global__ void __launch_bounds__(256)
+k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __restrict__ cnt,
+              const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items,
+              const BoxDev* __restrict__ boxes, int3 T, uint32_t* err) {
+    constexpr int K = Codes<NDIM>::K;
+    __shared__ uint32_t s_cnt[K];
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    const BoxDev& bx = boxes[w.box];
+    int tx, ty, tz;
+    tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
+    for (int c = threadIdx.x; c < K; c += blockDim.x) s_cnt[c] = 0;
+    __syncthreads();
+    uint32_t errbits = 0;
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
+        int i[3];
+        half_step_cell<Pol, NDIM>(P, j, bx, i);
+        int k = move_code<NDIM>(bx, T, tx, ty, tz, i, errbits);
+        code[j] = (uint16_t)(k | (bank_residue<NDIM>(bx, T, tx, ty, tz, k, i) << 5));
+        atomicAdd(&s_cnt[k], 1u);
+    }
+    if (errbits) latch(err, errbits);
+    __syncthreads();
+    for (int c = threadIdx.x; c < K; c += blockDim.x) cnt[(size_t)item * K + c] = s_cnt[c];
+}
+
+// Source tile of destination tile d for code k.
+template <int NDIM>
+__device__ __forceinline__ int source_tile(const BoxDev& bx, int d, int k) {
+    int tx, ty, tz;
+    tile_coords<NDIM>(bx, d, tx, ty, tz);
+    int cx = k % 3, cy = (k / 3) % 3, cz = NDIM == 3 ? k / 9 : 1;
+    int sx = pmod(tx - (cx - 1), bx.nt[0]);
+    int sy = pmod(ty - (cy - 1), bx.nt[1]);
+    int sz = NDIM == 3 ? pmod(tz - (cz - 1), bx.nt[2]) : 0;
+    return bx.tile_off + (sz * bx.nt[1] + sy) * bx.nt[0] + sx;
+}
+
+// Per destination tile: particles arriving from the (item, code) groups of
+// the current work list, and the number of next-step work items.
+template <int NDIM>
+__global__ void k_bin_count(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
+                            const int32_t* __restrict__ tile_box, const BoxDev* __restrict__ boxes,
+                            uint32_t* __restrict__ tile_count, uint32_t* __restrict__ tile_items,
+                            int NT, int P) {
+    constexpr int K = Codes<NDIM>::K;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= NT) return;
+    const BoxDev& bx = boxes[tile_box[d]];
+    uint32_t tot = 0;
+    for (int k = 0; k < K; ++k) {
+        int s = source_tile<NDIM>(bx, d, k);
+        for (uint32_t i = item_first[s]; i < item_first[s + 1]; ++i) tot += cnt[(size_t)i * K + k];
+    }
+    tile_count[d] = tot;
+    tile_items[d] = (tot + (uint32_t)P - 1) / (uint32_t)P;
+}
+
+// One block: exclusive scans of tile_count (-> start) and tile_items
+// (-> item_first_next, with the total in n_items_next).
+__global__ void __launch_bounds__(1024)
+k_scan2(const uint32_t* __restrict__ tile_count, const uint32_t* __restrict__ tile_items,
+        uint32_t* __restrict__ start, uint32_t* __restrict__ item_first_next,
+        uint32_t* __restrict__ n_items_next, int NT) {
+    __shared__ uint32_t s_a[1024], s_b[1024];
+    const int t = threadIdx.x;
+    const int per = (NT + 1023) / 1024;
+    const int t0 = min(t * per, NT), t1 = min(t0 + per, NT);
+    uint32_t sa = 0, sb = 0;
+    for (int i = t0; i < t1; ++i) {
+        sa += tile_count[i];
+        sb += tile_items[i];
+    }
+    s_a[t] = sa;
+    s_b[t] = sb;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t a = t >= o ? s_a[t - o] : 0u;
+        uint32_t b = t >= o ? s_b[t - o] : 0u;
+        __syncthreads();
+        s_a[t] += a;
+        s_b[t] += b;
+        __syncthreads();
+    }
+    uint32_t ra = s_a[t] - sa, rb = s_b[t] - sb;
+    for (int i = t0; i < t1; ++i) {
+        start[i] = ra;
+        item_first_next[i] = rb;
+        ra += tile_count[i];
+        rb += tile_items[i];
+    }
+    if (t == 1023) {
+        start[NT] = s_a[1023];
+        item_first_next[NT] = s_b[1023];
+        *n_items_next = s_b[1023];
+    }
+}
+
+// Per destination tile: the offset of every arriving (item, code) group and
+// the tile's next-step work items.
+template <int NDIM>
+__global__ void k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
+                              uint32_t* __restrict__ off, const int32_t* __restrict__ tile_box,
+                              const BoxDev* __restrict__ boxes, const uint32_t* __restrict__ start,
+                              const uint32_t* __restrict__ item_first_next,
+                              WorkItem* __restrict__ items_next, int NT, int P) {
+    constexpr int K = Codes<NDIM>::K;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= NT) return;
+    const BoxDev& bx = boxes[tile_box[d]];
+    const uint32_t s0 = start[d];
+    uint32_t run = s0;
+    for (int k = 0; k < K; ++k) {
+        int s = source_tile<NDIM>(bx, d, k);
+        for (uint32_t i = item_first[s]; i < item_first[s + 1]; ++i) {
+            off[(size_t)i * K + k] = run;
+            run += cnt[(size_t)i * K + k];
+        }
+    }
+    const uint32_t c = run - s0;
+    uint32_t io = item_first_next[d];
+    for (uint32_t q = 0; q < c; q += (uint32_t)P) {
+        WorkItem w;
+        w.tile = d;
+        w.begin = (int32_t)(s0 + q);
+        w.end = (int32_t)(s0 + min(q + (uint32_t)P, c));
+        w.box = tile_box[d];
+        items_next[io++] = w;
+    }
+}
+
+// Moves the particles of each current work item to their groups' offsets.
+// The item is moved in chunks of one particle per thread.  Within a chunk,
+// each group's particles are laid out level by level: level r holds the r-th
+// particle of every bank residue present, in residue order, so consecutive
+// particles (and lanes of the next push) fall on distinct LDS bank pairs while
+// the stores of a chunk stay within a window of the chunk's size.
+template <int NDIM, typename PS, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_bin_scatter(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
+              const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
+    constexpr int K = Codes<NDIM>::K;
+    constexpr int RS = kResidues;
+    __shared__ uint32_t s_n[K * RS];
+    __shared__ uint32_t s_run[K];
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
+    for (int c = threadIdx.x; c < K; c += BLOCK) s_run[c] = off[(size_t)item * K + c];
+    __syncthreads();
+    for (int base = w.begin; base < w.end; base += BLOCK) {
+        const int j = base + (int)threadIdx.x;
+        const bool act = j < w.end;
+        int k = 0, b = 0;
+        uint32_t lev = 0;
+        if (act) {
+            int cr = code[j];
+            k = cr & 31;
+            b = cr >> 5;
+            lev = atomicAdd(&s_n[k * RS + b], 1u);
+        }
+        __syncthreads();
+        uint32_t s = 0;
+        if (act) {
+            const uint32_t* nk = s_n + k * RS;
+            uint32_t pos = 0;
+#pragma unroll
+            for (int q = 0; q < RS; ++q) {
+                uint32_t nq = nk[q];
+                pos += min(nq, lev) + ((q < b && nq > lev) ? 1u : 0u);
+            }
+            s = s_run[k] + pos;
+        }
+        __syncthreads();
+        // advance the group bases by this chunk's counts and clear them
+        for (int c = threadIdx.x; c < K; c += BLOCK) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int q = 0; q < RS; ++q) t += s_n[c * RS + q];
+            s_run[c] += t;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
+        if (act) {
+            Bo.cell[s] = A.cell[j];
+            for (int d = 0; d < NDIM; ++d) Bo.d[d][s] = A.d[d][j];
+            for (int d = 0; d < 3; ++d) Bo.v[d][s] = A.v[d][j];
+            Bo.m[s] = A.m[j];
+            Bo.qm[s] = A.qm[j];
+            Bo.pid[s] = A.pid[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Initial sort: key = tile of the particle's current cell (any tile), with
+// global counters; used once per context.
+template <int NDIM, typename PS>
+__global__ void k_key_cell(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
+                           const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
+                           int nb, int64_t N, int3 T) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = j < N;
+    uint32_t k = 0;
+    if (act) {
+        const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+        int i[3];
+        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+        k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+        key[j] = k;
+    }
+    wave_claim(count, k, act);
+}
+
+}  // namespace mhdpic

@@ -27,6 +27,8 @@ struct BoxDev {
     int32_t nt[3];     // tiles per dimension
     int32_t tile_off;  // global index of this box's first tile
     int32_t hall;
+    int32_t small_last[3];  // 1: the last tile starts at n-2 (no 1-cell tiles)
+    int32_t pad0;
     int64_t cell_off;  // global index of this box's first cell
     int64_t part_off;  // first particle slot of this box
     int64_t part_n;    // particles in this box

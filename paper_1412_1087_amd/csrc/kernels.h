@@ -112,99 +112,42 @@ __global__ void k_init_convert(PS P, const double* __restrict__ x, const double*
     P.pid[j] = (int32_t)j;
 }
 
-// Deposits amount V over a 3^NDIM stencil straight into global int64 arrays.
-template <int NDIM>
-__device__ __forceinline__ void deposit_global(int64_t* dst, const BoxDev& bx, const int i[3],
-                                               const double wx[3], const double wy[3],
-                                               const double wz[3], double V) {
-    int64_t tot = quant1(V);
-    int64_t acc = 0;
-    const int zlo = NDIM == 3 ? 0 : 1, zhi = NDIM == 3 ? 2 : 1;
-    int64_t centre = 0;
-    for (int oz = zlo; oz <= zhi; ++oz)
-        for (int oy = 0; oy < 3; ++oy)
-            for (int ox = 0; ox < 3; ++ox) {
-                int cx = pmod(i[0] + ox - 1, bx.n[0]);
-                int cy = pmod(i[1] + oy - 1, bx.n[1]);
-                int cz = NDIM == 3 ? pmod(i[2] + oz - 1, bx.n[2]) : 0;
-                int64_t g = bx.cell_off + ((int64_t)cz * bx.n[1] + cy) * bx.n[0] + cx;
-                if (ox == 1 && oy == 1 && oz == 1) {
-                    centre = g;
-                    continue;
-                }
-                double wxy = wx[ox] * wy[oy];
-                double W = NDIM == 3 ? wxy * wz[oz] : wxy;
-                int64_t q = quant(W, V);
-                acc += q;
-                atomicAdd((unsigned long long*)&dst[g], (unsigned long long)q);
-            }
-    atomicAdd((unsigned long long*)&dst[centre], (unsigned long long)(tot - acc));
-}
-
-// n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
-// with global atomics; used once at initialisation.
-template <int NDIM>
-__global__ void k_deposit_nJ_global(PartF64 P, int64_t* __restrict__ nJ, int64_t NC,
-                                    const BoxDev* __restrict__ boxes,
-                                    const int64_t* __restrict__ part_off, int nb, int64_t N,
-                                    uint32_t* err) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-    int i[3];
-    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-    double wx[3], wy[3], wz[3] = {0.0, 1.0, 0.0};
-    tsc(P.d[0][j], wx);
-    tsc(P.d[1][j], wy);
-    if (NDIM == 3) tsc(P.d[2][j], wz);
-    double v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
-    Kin k = lorentz(v, bx.C, bx.C2, bx.iC);
-    double qmm = P.qm[j] * P.m[j];
-    double V[4] = {qmm * bx.S, (qmm * k.u[0]) * bx.S, (qmm * k.u[1]) * bx.S, (qmm * k.u[2]) * bx.S};
-    for (int c = 0; c < 4; ++c) {
-        if (!(fabs(V[c]) < kMaxAmount)) {
-            latch(err, ERRBIT_RANGE);
-            continue;
-        }
-        deposit_global<NDIM>(nJ + c * NC, bx, i, wx, wy, wz, V[c]);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // binning by tile of the half-step cell x^(n+1/2)
 // ---------------------------------------------------------------------------
 
+// Global index of cell (x, y, z) of a periodic box; coordinates may lie
+// outside [0, n) and are wrapped.
+template <int NDIM>
+__device__ __forceinline__ int64_t global_cell(const BoxDev& bx, int x, int y, int z) {
+    x = pmod(x, bx.n[0]);
+    y = pmod(y, bx.n[1]);
+    z = NDIM == 3 ? pmod(z, bx.n[2]) : 0;
+    return bx.cell_off + ((int64_t)z * bx.n[1] + y) * bx.n[0] + x;
+}
+
+// Tiles along a dimension start at multiples of T, except that when n % T == 1
+// the last tile starts at n - 2: every tile is at least two cells wide, so a
+// step (at most two cells) never crosses a whole tile.
+__device__ __forceinline__ int tile_index(const BoxDev& bx, int d, int i, int T) {
+    return (bx.small_last[d] && i >= bx.n[d] - 2) ? bx.nt[d] - 1 : i / T;
+}
+
+__device__ __forceinline__ int tile_origin(const BoxDev& bx, int d, int t, int T) {
+    return (bx.small_last[d] && t == bx.nt[d] - 1) ? bx.n[d] - 2 : t * T;
+}
+
+__device__ __forceinline__ int tile_extent(const BoxDev& bx, int d, int t, int T) {
+    int end = t == bx.nt[d] - 1 ? bx.n[d] : tile_origin(bx, d, t + 1, T);
+    return end - tile_origin(bx, d, t, T);
+}
+
 template <int NDIM>
 __device__ __forceinline__ uint32_t tile_of(const BoxDev& bx, const int3 T, int ix, int iy,
                                             int iz) {
-    int tx = ix / T.x, ty = iy / T.y, tz = NDIM == 3 ? iz / T.z : 0;
+    int tx = tile_index(bx, 0, ix, T.x), ty = tile_index(bx, 1, iy, T.y);
+    int tz = NDIM == 3 ? tile_index(bx, 2, iz, T.z) : 0;
     return (uint32_t)(bx.tile_off + (tz * bx.nt[1] + ty) * bx.nt[0] + tx);
-}
-
-// Key = tile of the cell reached by a half drift with this call's dt; the
-// push repeats the same operations, so it finds the particle in that tile.
-template <int NDIM, typename PS>
-__global__ void k_rekey(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                        const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
-                        int nb, int64_t N, int3 T) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = j < N;
-    uint32_t k = 0;
-    if (act) {
-        const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-        int i[3];
-        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-        double v[3] = {(double)P.v[0][j], (double)P.v[1][j], (double)P.v[2][j]};
-        Kin kn = lorentz(v, bx.C, bx.C2, bx.iC);
-        for (int d = 0; d < NDIM; ++d) {
-            double dl = (double)P.d[d][j];
-            int s = drift1(dl, kn.u[d], bx.hdx[d]);
-            i[d] = wrap_shift(i[d], s, bx.n[d]);
-        }
-        k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
-        key[j] = k;
-    }
-    wave_claim(count, k, act);
 }
 
 // Exclusive scan of tile counts and the work list: each tile's particles are
@@ -212,7 +155,8 @@ __global__ void k_rekey(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__
 __global__ void __launch_bounds__(1024)
 k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
        uint32_t* __restrict__ cursor, const int32_t* __restrict__ tile_box,
-       WorkItem* __restrict__ items, uint32_t* __restrict__ n_items, int NT, int P) {
+       WorkItem* __restrict__ items, uint32_t* __restrict__ item_first,
+       uint32_t* __restrict__ n_items, int NT, int P) {
     __shared__ uint32_t s_a[1024], s_b[1024];
     const int t = threadIdx.x;
     const int per = (NT + 1023) / 1024;
@@ -240,6 +184,7 @@ k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
         uint32_t c = count[i];
         start[i] = off;
         cursor[i] = off;
+        item_first[i] = io;
         for (uint32_t k = 0; k < c; k += (uint32_t)P) {
             WorkItem w;
             w.tile = i;
@@ -252,6 +197,7 @@ k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
     }
     if (t == 1023) {
         start[NT] = s_a[1023];
+        item_first[NT] = s_b[1023];
         *n_items = s_b[1023];
     }
 }
@@ -271,6 +217,84 @@ __global__ void k_scatter(PS A, PS Bo, const uint32_t* __restrict__ key,
     Bo.m[s] = A.m[j];
     Bo.qm[s] = A.qm[j];
     Bo.pid[s] = A.pid[j];
+}
+
+// ---------------------------------------------------------------------------
+// direction codes of tile-to-tile moves
+// ---------------------------------------------------------------------------
+
+template <int NDIM>
+struct Codes {
+    static constexpr int K = NDIM == 3 ? 27 : 9;
+    static constexpr int STAY = NDIM == 3 ? 13 : 4;
+};
+
+// Per-dimension code of a move from tile coordinate a to b on a ring of n
+// tiles: 1 = same, 2 = next, 0 = previous; -1 if farther.
+__device__ __forceinline__ int dir_code(int a, int b, int n) {
+    int d = b - a;
+    if (d < 0) d += n;
+    if (d == 0) return 1;
+    if (d == 1) return 2;
+    if (d == n - 1) return 0;
+    return -1;
+}
+
+template <int NDIM>
+__device__ __forceinline__ void tile_coords(const BoxDev& bx, int tile, int& tx, int& ty, int& tz) {
+    int lt = tile - bx.tile_off;
+    tx = lt % bx.nt[0];
+    ty = (lt / bx.nt[0]) % bx.nt[1];
+    tz = NDIM == 3 ? lt / (bx.nt[0] * bx.nt[1]) : 0;
+}
+
+// Code of the move from the item's tile (tx,ty,tz) to the tile holding cell i;
+// Codes::STAY (and an error bit) if the cell is farther than one tile.
+template <int NDIM>
+__device__ __forceinline__ int move_code(const BoxDev& bx, int3 T, int tx, int ty, int tz,
+                                         const int i[3], uint32_t& errbits) {
+    int cx = dir_code(tx, tile_index(bx, 0, i[0], T.x), bx.nt[0]);
+    int cy = dir_code(ty, tile_index(bx, 1, i[1], T.y), bx.nt[1]);
+    int cz = NDIM == 3 ? dir_code(tz, tile_index(bx, 2, i[2], T.z), bx.nt[2]) : 0;
+    if (cx < 0 || cy < 0 || cz < 0) {
+        errbits |= ERRBIT_STATE;
+        return Codes<NDIM>::STAY;
+    }
+    return NDIM == 3 ? (cz * 3 + cy) * 3 + cx : cy * 3 + cx;
+}
+
+// Bank residue of the cell ni in the LDS geometry of the destination tile of
+// code k (strides T.x + 4, T.y + 4, ghost width 2).  64-bit words of equal
+// residue share a bank pair; the binning orders particles so that 16
+// consecutive lanes have distinct residues.
+#ifndef MHDPIC_RESIDUES
+#define MHDPIC_RESIDUES 16
+#endif
+constexpr int kResidues = MHDPIC_RESIDUES;
+
+__device__ __forceinline__ int ring(int t, int n) { return t < 0 ? t + n : (t >= n ? t - n : t); }
+
+template <int NDIM>
+__device__ __forceinline__ int bank_residue(const BoxDev& bx, int3 T, int tx, int ty, int tz, int k,
+                                            const int ni[3]) {
+    int dx = ring(tx + k % 3 - 1, bx.nt[0]);
+    int dy = ring(ty + (k / 3) % 3 - 1, bx.nt[1]);
+    int dz = NDIM == 3 ? ring(tz + k / 9 - 1, bx.nt[2]) : 0;
+    int lx = ni[0] - tile_origin(bx, 0, dx, T.x) + 2;
+    int ly = ni[1] - tile_origin(bx, 1, dy, T.y) + 2;
+    int idx = ly * (T.x + 4) + lx;
+    if (NDIM == 3) idx += (ni[2] - tile_origin(bx, 2, dz, T.z) + 2) * (T.x + 4) * (T.y + 4);
+    return idx & (kResidues - 1);
+}
+
+__device__ __forceinline__ bool item_of_block(const uint32_t* n_items, uint32_t& item) {
+    const uint32_t nitems = *n_items;
+    const uint32_t per_xcd = (nitems + 7u) / 8u;
+    const uint32_t bid = blockIdx.x;
+    const uint32_t slot = bid >> 3;
+    if (slot >= per_xcd) return false;
+    item = (bid & 7u) * per_xcd + slot;
+    return item < nitems;
 }
 
 // ---------------------------------------------------------------------------

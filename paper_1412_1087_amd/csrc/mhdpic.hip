@@ -20,8 +20,8 @@
 #include "../../include/mhdpic.h"
 #include "common.h"
 #include "kernels.h"
-#include "push_f64.h"
-#include "push_f32.h"
+#include "push.h"
+#include "binning.h"
 
 using namespace mhdpic;
 
@@ -74,8 +74,11 @@ struct Layout {
     int32_t NT = 0, NW = 0;
     // offsets into the workspace
     size_t partA = 0, partB = 0, part_bytes = 0;
-    size_t key = 0, EB = 0, Dcorr = 0, nJ0 = 0, nJ1 = 0;
-    size_t count = 0, start = 0, cursor = 0, tile_box = 0, items = 0, n_items = 0, err = 0;
+    size_t key = 0, code = 0, EB = 0, Dcorr = 0, nJ0 = 0, nJ1 = 0;
+    size_t count = 0, start = 0, cursor = 0, tile_box = 0, err = 0;
+    size_t items[2] = {0, 0}, n_items[2] = {0, 0}, item_first[2] = {0, 0};
+    size_t cnt = 0, off = 0;
+    int K = 27;
     size_t boxes = 0, part_off = 0, cell_off = 0;
     size_t total = 0;
 };
@@ -91,11 +94,20 @@ struct mhdpic_ctx {
     Layout L;
     unsigned char* ws = nullptr;
     int cur = 0;   // which particle buffer (0 = A, 1 = B) holds the state
+    int it = 0;    // which work list describes that buffer
     int nj = 0;    // which nJ buffer is current
     hipStream_t last_stream = nullptr;
     uint32_t* err_host = nullptr;  // pinned copy of the error word
     hipEvent_t err_event = nullptr;
     bool err_pending = false;
+    // optional per-phase timing
+    bool timing = false;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace {
@@ -169,7 +181,9 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     };
     L.partA = take(L.part_bytes);
     L.partB = take(L.part_bytes);
+    L.K = ndim == 3 ? 27 : 9;
     L.key = take(N * 4);
+    L.code = take(N * 2);
     L.EB = take(NC * 6 * fsz);
     L.Dcorr = take(NC * 4 * 8);
     L.nJ0 = take(NC * 4 * 8);
@@ -178,8 +192,13 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     L.start = take((size_t)(L.NT + 1) * 4);
     L.cursor = take((size_t)L.NT * 4);
     L.tile_box = take((size_t)L.NT * 4);
-    L.items = take((size_t)L.NW * sizeof(WorkItem));
-    L.n_items = take(4);
+    for (int q = 0; q < 2; ++q) {
+        L.items[q] = take((size_t)L.NW * sizeof(WorkItem));
+        L.n_items[q] = take(4);
+        L.item_first[q] = take((size_t)(L.NT + 1) * 4);
+    }
+    L.cnt = take((size_t)L.NW * L.K * 4);
+    L.off = take((size_t)L.NW * L.K * 4);
     L.err = take(4);
     L.boxes = take((size_t)nb * sizeof(BoxDev));
     L.part_off = take((size_t)(nb + 1) * 8);
@@ -262,6 +281,11 @@ const char* msg_of(uint32_t bits) {
 // launch helpers, dispatched on (ndim, precision, tile)
 // ---------------------------------------------------------------------------
 
+unsigned item_grid(const Layout& L) { return (unsigned)((L.NW + 7) / 8 * 8); }
+
+// Re-bins the particles of the current buffer into the other one.  With
+// rekey, the direction codes are first recomputed for this call's dt;
+// otherwise the push has just written them.
 template <int NDIM, typename PS, typename T>
 int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
     const Layout& L = c->L;
@@ -269,82 +293,95 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
     PS A = part<PS, T>(c, c->cur);
     PS Bo = part<PS, T>(c, 1 - c->cur);
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
-    const int64_t* po = at<int64_t>(c, L.part_off);
-    if (rekey) {
-        fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
-        if (L.N > 0) {
-            if constexpr (std::is_same<PS, PartF64>::value)
-                hipLaunchKernelGGL((k_rekey<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
-                                   at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), bd, po, c->nb, L.N, T3);
-            else
-                hipLaunchKernelGGL((k_rekey_f32<NDIM>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
-                                   at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), bd, po, c->nb, L.N, T3);
-        }
-    }
+    const int it = c->it;
+    using Pol = typename std::conditional<std::is_same<PS, PartF64>::value, F64Pol, F32Pol>::type;
+    if (rekey)
+        hipLaunchKernelGGL((k_rekey_items<Pol, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
+                           at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
+                           at<uint32_t>(c, L.n_items[it]), bd, T3, at<uint32_t>(c, L.err));
+    const unsigned gT = grid_for(L.NT, 256);
+    hipLaunchKernelGGL(k_bin_count<NDIM>, dim3(gT), dim3(256), 0, s, at<uint32_t>(c, L.cnt),
+                       at<uint32_t>(c, L.item_first[it]), at<int32_t>(c, L.tile_box), bd,
+                       at<uint32_t>(c, L.count), at<uint32_t>(c, L.cursor), L.NT, kItemParticles);
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
+                       at<uint32_t>(c, L.cursor), at<uint32_t>(c, L.start),
+                       at<uint32_t>(c, L.item_first[1 - it]), at<uint32_t>(c, L.n_items[1 - it]), L.NT);
+    hipLaunchKernelGGL(k_bin_offsets<NDIM>, dim3(gT), dim3(256), 0, s, at<uint32_t>(c, L.cnt),
+                       at<uint32_t>(c, L.item_first[it]), at<uint32_t>(c, L.off),
+                       at<int32_t>(c, L.tile_box), bd, at<uint32_t>(c, L.start),
+                       at<uint32_t>(c, L.item_first[1 - it]), at<WorkItem>(c, L.items[1 - it]),
+                       L.NT, kItemParticles);
+    hipLaunchKernelGGL((k_bin_scatter<NDIM, PS, 256>), dim3(item_grid(L)), dim3(256), 0, s, A, Bo,
+                       at<uint16_t>(c, L.code), at<uint32_t>(c, L.off), at<WorkItem>(c, L.items[it]),
+                       at<uint32_t>(c, L.n_items[it]));
+    c->cur = 1 - c->cur;
+    c->it = 1 - it;
+    return MHDPIC_OK;
+}
+
+// First binning of a new context: any tile, by the particles' current cells,
+// from buffer 0 into buffer 1.
+template <int NDIM, typename PS, typename T>
+int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
+    const Layout& L = c->L;
+    const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
+    PS A = part<PS, T>(c, 0);
+    PS Bo = part<PS, T>(c, 1);
+    fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
+    if (L.N > 0)
+        hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
+                           at<int64_t>(c, L.part_off), c->nb, L.N, T3);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
                        at<uint32_t>(c, L.start), at<uint32_t>(c, L.cursor), at<int32_t>(c, L.tile_box),
-                       at<WorkItem>(c, L.items), at<uint32_t>(c, L.n_items), L.NT, kItemParticles);
+                       at<WorkItem>(c, L.items[0]), at<uint32_t>(c, L.item_first[0]),
+                       at<uint32_t>(c, L.n_items[0]), L.NT, kItemParticles);
     if (L.N > 0)
         hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A, Bo,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N);
-    c->cur = 1 - c->cur;
+    c->cur = 1;
+    c->it = 0;
     return MHDPIC_OK;
 }
 
-template <int NDIM, int TX, int TY, int TZ>
-int launch_push_f64_t(mhdpic_ctx* c, hipStream_t s) {
+int launch_initial_sort_any(mhdpic_ctx* c, hipStream_t s) {
+    if (c->precision == MHDPIC_FP64) {
+        if (c->ndim == 2) return launch_initial_sort<2, PartF64, double>(c, s);
+        return launch_initial_sort<3, PartF64, double>(c, s);
+    }
+    if (c->ndim == 2) return launch_initial_sort<2, PartF32, float>(c, s);
+    return launch_initial_sort<3, PartF32, float>(c, s);
+}
+
+template <class Pol, int NDIM, int TX, int TY, int TZ>
+int launch_push_pol(mhdpic_ctx* c, hipStream_t s) {
     constexpr int BLOCK = 256;
-    using TL = Tiling<NDIM, TX, TY, TZ>;
+    using G = Geo<Pol, NDIM, TX, TY, TZ>;
+    using R = typename Pol::R;
     const Layout& L = c->L;
-    PushArgs a;
-    a.P = part<PartF64, double>(c, c->cur);
-    a.key = at<uint32_t>(c, L.key);
-    a.count = at<uint32_t>(c, L.count);
-    a.EB = at<double>(c, L.EB);
+    PushArgsT<Pol> a;
+    a.P = part<typename Pol::Part, R>(c, c->cur);
+    a.code = at<uint16_t>(c, L.code);
+    a.cnt = at<uint32_t>(c, L.cnt);
+    a.EB = at<R>(c, L.EB);
     a.Dcorr = at<int64_t>(c, L.Dcorr);
     a.nJ = at<int64_t>(c, c->nj == 0 ? L.nJ1 : L.nJ0);  // next buffer
     a.boxes = at<BoxDev>(c, L.boxes);
-    a.items = at<WorkItem>(c, L.items);
-    a.n_items = at<uint32_t>(c, L.n_items);
+    a.items = at<WorkItem>(c, L.items[c->it]);
+    a.n_items = at<uint32_t>(c, L.n_items[c->it]);
     a.err = at<uint32_t>(c, L.err);
     a.NC = L.NC;
-    size_t lds = TL::lds_bytes();
-    auto kern = k_push_f64<NDIM, TX, TY, TZ, BLOCK>;
+    size_t lds = G::lds_bytes();
+    auto kern = k_push<Pol, NDIM, TX, TY, TZ, BLOCK>;
     if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    unsigned grid = (unsigned)((L.NW + 7) / 8 * 8);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
-    return MHDPIC_OK;
-}
-
-template <int NDIM, int TX, int TY, int TZ>
-int launch_push_f32_t(mhdpic_ctx* c, hipStream_t s) {
-    constexpr int BLOCK = 256;
-    using TL = Tiling32<NDIM, TX, TY, TZ>;
-    const Layout& L = c->L;
-    PushArgs32 a;
-    a.P = part<PartF32, float>(c, c->cur);
-    a.key = at<uint32_t>(c, L.key);
-    a.count = at<uint32_t>(c, L.count);
-    a.EB = at<float>(c, L.EB);
-    a.Dcorr = at<int64_t>(c, L.Dcorr);
-    a.nJ = at<int64_t>(c, c->nj == 0 ? L.nJ1 : L.nJ0);
-    a.boxes = at<BoxDev>(c, L.boxes);
-    a.items = at<WorkItem>(c, L.items);
-    a.n_items = at<uint32_t>(c, L.n_items);
-    a.err = at<uint32_t>(c, L.err);
-    a.NC = L.NC;
-    size_t lds = TL::lds_bytes();
-    auto kern = k_push_f32<NDIM, TX, TY, TZ, BLOCK>;
-    if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    unsigned grid = (unsigned)((L.NW + 7) / 8 * 8);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s, a);
     return MHDPIC_OK;
 }
 
 template <int NDIM, int TX, int TY, int TZ>
 int launch_push_t(mhdpic_ctx* c, hipStream_t s) {
-    if (c->precision == MHDPIC_FP64) return launch_push_f64_t<NDIM, TX, TY, TZ>(c, s);
-    return launch_push_f32_t<NDIM, TX, TY, TZ>(c, s);
+    if (c->precision == MHDPIC_FP64) return launch_push_pol<F64Pol, NDIM, TX, TY, TZ>(c, s);
+    return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s);
 }
 
 int launch_push(mhdpic_ctx* c, hipStream_t s) {
@@ -388,6 +425,35 @@ int launch_fieldprep(mhdpic_ctx* c, const double* B, const double* vg, const dou
                            at<int64_t>(c, L.cell_off), c->nb, L.NC);
     return MHDPIC_OK;
 }
+
+// Event pair around a phase when timing is on.
+struct PhaseTimer {
+    mhdpic_ctx* c;
+    hipStream_t s;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipEvent_t take() {
+        if (!c->pool.empty()) {
+            hipEvent_t e = c->pool.back();
+            c->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    PhaseTimer(mhdpic_ctx* c_, hipStream_t s_, int phase_) : c(c_), s(s_), phase(phase_) {
+        if (!c->timing) return;
+        a = take();
+        b = take();
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~PhaseTimer() {
+        if (!c->timing || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        c->marks.push_back({phase, a, b});
+    }
+};
 
 // Pick up a device error latched by earlier work, without waiting for it.
 int poll_error(mhdpic_ctx* c) {
@@ -466,7 +532,10 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
             d.x0[k] = (k < ndim) ? B.x0[k] : 0.0;
         }
         int T[3] = {tile.x, tile.y, ndim == 3 ? tile.z : 1};
-        for (int k = 0; k < 3; ++k) d.nt[k] = (d.n[k] + T[k] - 1) / T[k];
+        for (int k = 0; k < 3; ++k) {
+            d.nt[k] = (d.n[k] + T[k] - 1) / T[k];
+            d.small_last[k] = (d.nt[k] >= 2 && d.n[k] % T[k] == 1) ? 1 : 0;
+        }
         d.tile_off = toff;
         int ntiles = d.nt[0] * d.nt[1] * d.nt[2];
         for (int t = 0; t < ntiles; ++t) tile_box.push_back(b);
@@ -526,34 +595,46 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
     c->nj = 0;
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
     const int64_t* po = at<int64_t>(c, L.part_off);
+    const unsigned gN = grid_for(L.N, 256);
     if (L.N > 0) {
         if (precision == MHDPIC_FP64) {
             PartF64 P = part<PartF64, double>(c, 0);
             if (ndim == 2)
-                hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(gN), dim3(256), 0, s,
                                    P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
             else
-                hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(gN), dim3(256), 0, s,
                                    P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            if (ndim == 2)
-                hipLaunchKernelGGL(k_deposit_nJ_global<2>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            else
-                hipLaunchKernelGGL(k_deposit_nJ_global<3>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
         } else {
             PartF32 P = part<PartF32, float>(c, 0);
             if (ndim == 2)
-                hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(gN), dim3(256), 0, s,
                                    P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
             else
-                hipLaunchKernelGGL((k_init_convert<3, PartF32, float>), dim3(grid_for(L.N, 256)), dim3(256), 0, s,
+                hipLaunchKernelGGL((k_init_convert<3, PartF32, float>), dim3(gN), dim3(256), 0, s,
                                    P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+        }
+    }
+    {
+        int rc0 = launch_initial_sort_any(c, s);
+        if (rc0) return cleanup(rc0);
+    }
+    if (L.N > 0) {
+        if (precision == MHDPIC_FP64) {
+            PartF64 P = part<PartF64, double>(c, c->cur);
             if (ndim == 2)
-                hipLaunchKernelGGL(k_deposit_nJ_global_f32<2>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                hipLaunchKernelGGL((k_deposit_nJ_global<F64Pol, 2>), dim3(gN), dim3(256), 0, s, P,
                                    at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
             else
-                hipLaunchKernelGGL(k_deposit_nJ_global_f32<3>, dim3(grid_for(L.N, 256)), dim3(256), 0, s, P,
+                hipLaunchKernelGGL((k_deposit_nJ_global<F64Pol, 3>), dim3(gN), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+        } else {
+            PartF32 P = part<PartF32, float>(c, c->cur);
+            if (ndim == 2)
+                hipLaunchKernelGGL((k_deposit_nJ_global<F32Pol, 2>), dim3(gN), dim3(256), 0, s, P,
+                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
+            else
+                hipLaunchKernelGGL((k_deposit_nJ_global<F32Pol, 3>), dim3(gN), dim3(256), 0, s, P,
                                    at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
         }
     }
@@ -602,18 +683,30 @@ int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* 
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
                            hipMemcpyHostToDevice, s));
     if (!rho) rho = B;  // never read without the Hall term
-    rc = launch_bin_any(c, s, true);
+    {
+        PhaseTimer t(c, s, 0);
+        rc = launch_bin_any(c, s, true);
+    }
     if (rc) return rc;
     for (int st = 0; st < n_steps; ++st) {
-        rc = launch_fieldprep(c, B, vg, rho, s);
+        {
+            PhaseTimer t(c, s, 1);
+            rc = launch_fieldprep(c, B, vg, rho, s);
+        }
         if (rc) return rc;
-        int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
-        fill_i64(next, 4 * c->L.NC, s);
-        fill_u32(at<uint32_t>(c, c->L.count), c->L.NT, 0u, s);
-        rc = launch_push(c, s);
+        {
+            PhaseTimer t(c, s, 3);
+            int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
+            fill_i64(next, 4 * c->L.NC, s);
+        }
+        {
+            PhaseTimer t(c, s, 2);
+            rc = launch_push(c, s);
+        }
         if (rc) return rc;
         c->nj = 1 - c->nj;
         if (st + 1 < n_steps) {
+            PhaseTimer t(c, s, 0);
             rc = launch_bin_any(c, s, false);
             if (rc) return rc;
         }
@@ -674,8 +767,39 @@ int mhdpic_check(mhdpic_ctx* c, void* hip_stream) {
     return MHDPIC_OK;
 }
 
+int mhdpic_timing_enable(mhdpic_ctx* c, int32_t enable) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return MHDPIC_OK;
+}
+
+int mhdpic_timing_read(mhdpic_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return fail(MHDPIC_EINVAL, "NULL argument");
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto& mk : c->marks) {
+        HIP_TRY(hipEventSynchronize(mk.b));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, mk.a, mk.b));
+        ms[mk.phase] += t;
+        launches[mk.phase] += 1;
+        c->pool.push_back(mk.a);
+        c->pool.push_back(mk.b);
+    }
+    c->marks.clear();
+    return MHDPIC_OK;
+}
+
 int mhdpic_destroy(mhdpic_ctx* c) {
     if (!c) return MHDPIC_OK;
+    for (auto& mk : c->marks) {
+        (void)hipEventSynchronize(mk.b);
+        c->pool.push_back(mk.a);
+        c->pool.push_back(mk.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->err_event) {
         (void)hipEventSynchronize(c->err_event);
         (void)hipEventDestroy(c->err_event);

@@ -1,0 +1,351 @@
+// Fused gather + Boris push + deposit (App. A.2, A.3), both precision forms.
+//
+// One work item = up to P particles whose half-step cell x^(n+1/2) lies in one
+// tile of TX x TY (x TZ) cells.  The block stages three LDS boxes on one index
+// geometry, the tile plus two ghost layers (strides PX = TX+4, PY = TY+4):
+//   F  : E and B of the tile plus one ghost layer, [6][cells];
+//   Dc : -dM, -dE_k at x^(n+1/2), same cells as F, [4][cells] int64;
+//   Dp : n_CR, J_CR at x^(n+1), all cells, [4][cells] int64.
+// F and Dc skip the outermost plane (rows in 2D) on each side, which they
+// never touch.  Because the three boxes share strides, a particle's cell has
+// the same LDS bank in all of them; the binning orders particles so that 16
+// consecutive lanes have distinct bank residues.
+//
+// Each particle's 3^NDIM contributions per channel go to LDS with 64-bit
+// integer atomics; the block then adds the non-zero LDS cells to the global
+// arrays with 64-bit atomics.  Integer sums make the result independent of the
+// order in which particles, waves and blocks run.
+#pragma once
+#include "kernels.h"
+
+namespace mhdpic {
+
+template <class Pol>
+struct PushArgsT {
+    typename Pol::Part P;        // tile-sorted particles, updated in place
+    uint16_t* code;              // out: direction code | bank residue << 5
+    uint32_t* cnt;               // out: [item][code] particle counts
+    const typename Pol::R* EB;   // [cells][6] E and B
+    int64_t* Dcorr;              // [4][cells] accumulated -dM, -dE_k
+    int64_t* nJ;                 // [4][cells] n_CR, J_CR at x^(n+1) (pre-zeroed)
+    const BoxDev* boxes;
+    const WorkItem* items;
+    const uint32_t* n_items;
+    uint32_t* err;
+    int64_t NC;
+};
+
+template <class Pol, int NDIM, int TX, int TY, int TZ>
+struct Geo {
+    using R = typename Pol::R;
+    static constexpr int PX = TX + 4, PY = TY + 4, PZ = NDIM == 3 ? TZ + 4 : 1;
+    static constexpr int NP = PX * PY * PZ;
+    static constexpr int FOFF = NDIM == 3 ? PX * PY : PX;  // skipped leading plane/row
+    static constexpr int NFF = NP - 2 * FOFF;
+    static constexpr int CORNER = NDIM == 3 ? PX * PY + PX + 1 : PX + 1;
+    static constexpr size_t lds_bytes() {
+        return (size_t)NFF * 4 * 8 + (size_t)NP * 4 * 8 + (size_t)NFF * 6 * sizeof(R);
+    }
+    // index of tile-local cell (lx, ly, lz), each in [-2, extent + 2)
+    __device__ static __forceinline__ int index(int lx, int ly, int lz) {
+        return NDIM == 3 ? ((lz + 2) * PY + (ly + 2)) * PX + (lx + 2) : (ly + 2) * PX + (lx + 2);
+    }
+    __device__ static __forceinline__ void coords(int p, int& lx, int& ly, int& lz) {
+        lx = p % PX - 2;
+        ly = (p / PX) % PY - 2;
+        lz = NDIM == 3 ? p / (PX * PY) - 2 : 0;
+    }
+};
+
+// Adds 4 channel amounts V[0..3] of one particle to an LDS box [4][NB] whose
+// (-1,-1,-1) stencil corner is at index `base`; weights in the working
+// precision, quantised against the binary64 amounts.
+template <class Pol, int NDIM, int SX, int SY, int NB>
+__device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
+                                             const typename Pol::R wx[3],
+                                             const typename Pol::R wy[3],
+                                             const typename Pol::R wz[3], const double V[4]) {
+    using R = typename Pol::R;
+    int64_t acc[4] = {0, 0, 0, 0};
+    int64_t tot[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tot[c] = quant1(V[c]);
+    unsigned long long* p0 = box + base;
+    constexpr int ZN = NDIM == 3 ? 3 : 1;
+#pragma unroll 1
+    for (int oz = 0; oz < ZN; ++oz) {
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const bool centre = ox == 1 && oy == 1 && (NDIM == 2 || oz == 1);
+                if (centre) continue;
+                R wxy = wx[ox] * wy[oy];
+                double W = (double)(NDIM == 3 ? wxy * wz[oz] : wxy);
+                unsigned long long* p = p0 + (oz * SY + oy) * SX + ox;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    int64_t q = quant(W, V[c]);
+                    acc[c] += q;
+                    atomicAdd(p + c * NB, (unsigned long long)q);
+                }
+            }
+        }
+    }
+    constexpr int CZ = NDIM == 3 ? 1 : 0;
+    unsigned long long* pc = p0 + (CZ * SY + 1) * SX + 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) atomicAdd(pc + c * NB, (unsigned long long)(tot[c] - acc[c]));
+}
+
+template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
+    using G = Geo<Pol, NDIM, TX, TY, TZ>;
+    using R = typename Pol::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long* Dc = reinterpret_cast<unsigned long long*>(smem);
+    unsigned long long* Dp = Dc + (size_t)G::NFF * 4;
+    R* F = reinterpret_cast<R*>(Dp + (size_t)G::NP * 4);
+    constexpr int K = Codes<NDIM>::K;
+    __shared__ uint32_t s_cnt[K];
+
+    uint32_t item;
+    if (!item_of_block(a.n_items, item)) return;
+    for (int c = threadIdx.x; c < K; c += BLOCK) s_cnt[c] = 0;
+    const WorkItem w = a.items[item];
+    const BoxDev& bx = a.boxes[w.box];
+    int tx, ty, tz;
+    tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
+    const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);
+    const int oz = NDIM == 3 ? tile_origin(bx, 2, tz, TZ) : 0;
+    const int sx = tile_extent(bx, 0, tx, TX), sy = tile_extent(bx, 1, ty, TY);
+    const int sz = NDIM == 3 ? tile_extent(bx, 2, tz, TZ) : 1;
+
+    // stage E, B of the tile + 1 ghost layer; zero the deposit boxes
+    for (int c = threadIdx.x; c < G::NFF; c += BLOCK) {
+        int lx, ly, lz;
+        G::coords(c + G::FOFF, lx, ly, lz);
+        bool in = lx >= -1 && lx <= sx && ly >= -1 && ly <= sy && (NDIM == 2 || (lz >= -1 && lz <= sz));
+        if (in) {
+            int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+            const R* s = a.EB + 6 * g;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) F[q * G::NFF + c] = s[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Dc[q * G::NFF + c] = 0ull;
+    }
+    for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
+    __syncthreads();
+
+    const double C = bx.C, C2 = bx.C2, iC = bx.iC, S = bx.S, hdt = bx.hdt;
+    const R hx = Pol::hdx(bx.hdx[0]), hy = Pol::hdx(bx.hdx[1]), hz = Pol::hdx(bx.hdx[2]);
+    const int3 T = make_int3(TX, TY, TZ);
+    uint32_t errbits = 0;
+
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        int i[3];
+        unpack_cell<NDIM>(a.P.cell[j], i[0], i[1], i[2]);
+        R dl[3] = {a.P.d[0][j], a.P.d[1][j], NDIM == 3 ? a.P.d[2][j] : R(0)};
+        R v[3] = {a.P.v[0][j], a.P.v[1][j], a.P.v[2][j]};
+        const double m = (double)a.P.m[j], qm = (double)a.P.qm[j];
+
+        typename Pol::K k0 = Pol::kin(v, C, C2, iC);
+        // drift to x^(n+1/2)
+        int s0 = Pol::drift(dl[0], k0.u[0], hx);
+        int s1 = Pol::drift(dl[1], k0.u[1], hy);
+        int s2 = NDIM == 3 ? Pol::drift(dl[2], k0.u[2], hz) : 0;
+        i[0] = wrap_shift(i[0], s0, bx.n[0]);
+        i[1] = wrap_shift(i[1], s1, bx.n[1]);
+        if (NDIM == 3) i[2] = wrap_shift(i[2], s2, bx.n[2]);
+        int lx = i[0] - ox, ly = i[1] - oy, lz = NDIM == 3 ? i[2] - oz : 0;
+        bool inside = lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz;
+        if (!inside) {
+            errbits |= ERRBIT_STATE;
+            lx = min(max(lx, 0), sx - 1);
+            ly = min(max(ly, 0), sy - 1);
+            lz = NDIM == 3 ? min(max(lz, 0), sz - 1) : 0;
+        }
+        const int corner = G::index(lx, ly, lz) - G::CORNER;  // (-1,-1,-1) neighbour
+        const int fbase = corner - G::FOFF;
+
+        // TSC gather of E, B at x^(n+1/2)
+        R wx[3], wy[3], wz[3] = {R(0), R(1), R(0)};
+        Pol::weights(dl[0], wx);
+        Pol::weights(dl[1], wy);
+        if (NDIM == 3) Pol::weights(dl[2], wz);
+        R E[3] = {R(0), R(0), R(0)}, Bp[3] = {R(0), R(0), R(0)};
+        constexpr int ZN = NDIM == 3 ? 3 : 1;
+#pragma unroll 1
+        for (int oz2 = 0; oz2 < ZN; ++oz2) {
+#pragma unroll
+            for (int oy2 = 0; oy2 < 3; ++oy2) {
+#pragma unroll
+                for (int ox2 = 0; ox2 < 3; ++ox2) {
+                    R wxy = wx[ox2] * wy[oy2];
+                    R W = NDIM == 3 ? wxy * wz[oz2] : wxy;
+                    const R* f = F + fbase + (oz2 * G::PY + oy2) * G::PX + ox2;
+                    E[0] = Pol::fma(W, f[0 * G::NFF], E[0]);
+                    E[1] = Pol::fma(W, f[1 * G::NFF], E[1]);
+                    E[2] = Pol::fma(W, f[2 * G::NFF], E[2]);
+                    Bp[0] = Pol::fma(W, f[3 * G::NFF], Bp[0]);
+                    Bp[1] = Pol::fma(W, f[4 * G::NFF], Bp[1]);
+                    Bp[2] = Pol::fma(W, f[5 * G::NFF], Bp[2]);
+                }
+            }
+        }
+        Pol::clean(E, Bp);
+
+        // kick - rotate - kick
+        R vn[3];
+        Pol::push(v, E, Bp, qm * hdt, C, C2, vn);
+        if (!isfinite(vn[0]) || !isfinite(vn[1]) || !isfinite(vn[2])) errbits |= ERRBIT_NONFINITE;
+        typename Pol::K k1 = Pol::kin(vn, C, C2, iC);
+
+        // corrector feedback at x^(n+1/2): -dM, -dE_k (App. A.3)
+        double Vc[4];
+        Vc[0] = (-(m * ((double)vn[0] - (double)v[0]))) * S;
+        Vc[1] = (-(m * ((double)vn[1] - (double)v[1]))) * S;
+        Vc[2] = (-(m * ((double)vn[2] - (double)v[2]))) * S;
+        Vc[3] = (-(m * (k1.ek - k0.ek))) * S;
+        bool okc = fabs(Vc[0]) < kMaxAmount && fabs(Vc[1]) < kMaxAmount &&
+                   fabs(Vc[2]) < kMaxAmount && fabs(Vc[3]) < kMaxAmount;
+        if (okc) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NFF>(Dc, fbase, wx, wy, wz, Vc);
+        else errbits |= ERRBIT_RANGE;
+
+        // drift to x^(n+1)
+        int t0 = Pol::drift(dl[0], k1.u[0], hx);
+        int t1 = Pol::drift(dl[1], k1.u[1], hy);
+        int t2 = NDIM == 3 ? Pol::drift(dl[2], k1.u[2], hz) : 0;
+        i[0] = wrap_shift(i[0], t0, bx.n[0]);
+        i[1] = wrap_shift(i[1], t1, bx.n[1]);
+        if (NDIM == 3) i[2] = wrap_shift(i[2], t2, bx.n[2]);
+        const int pbase = corner + (NDIM == 3 ? (t2 * G::PY + t1) * G::PX + t0 : t1 * G::PX + t0);
+
+        // n_CR, J_CR at x^(n+1): the predictor input of the next step
+        Pol::weights(dl[0], wx);
+        Pol::weights(dl[1], wy);
+        if (NDIM == 3) Pol::weights(dl[2], wz);
+        const double qmm = qm * m;
+        double Vp[4];
+        Vp[0] = qmm * S;
+        Vp[1] = (qmm * (double)k1.u[0]) * S;
+        Vp[2] = (qmm * (double)k1.u[1]) * S;
+        Vp[3] = (qmm * (double)k1.u[2]) * S;
+        bool okp = fabs(Vp[0]) < kMaxAmount && fabs(Vp[1]) < kMaxAmount &&
+                   fabs(Vp[2]) < kMaxAmount && fabs(Vp[3]) < kMaxAmount;
+        if (okp) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
+        else errbits |= ERRBIT_RANGE;
+
+        // store x^(n+1), v^(n+1)
+        a.P.cell[j] = pack_cell<NDIM>(i[0], i[1], i[2]);
+        a.P.d[0][j] = dl[0];
+        a.P.d[1][j] = dl[1];
+        if (NDIM == 3) a.P.d[2][j] = dl[2];
+        a.P.v[0][j] = vn[0];
+        a.P.v[1][j] = vn[1];
+        a.P.v[2][j] = vn[2];
+
+        // tile and bank residue of the next half-step cell (the operations of
+        // the next step's first drift)
+        int ni[3] = {i[0], i[1], i[2]};
+        R e0 = dl[0], e1 = dl[1], e2 = dl[2];
+        ni[0] = wrap_shift(ni[0], Pol::drift(e0, k1.u[0], hx), bx.n[0]);
+        ni[1] = wrap_shift(ni[1], Pol::drift(e1, k1.u[1], hy), bx.n[1]);
+        if (NDIM == 3) ni[2] = wrap_shift(ni[2], Pol::drift(e2, k1.u[2], hz), bx.n[2]);
+        const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits);
+        a.code[j] = (uint16_t)(k | (bank_residue<NDIM>(bx, T, tx, ty, tz, k, ni) << 5));
+        atomicAdd(&s_cnt[k], 1u);
+    }
+    if (errbits) latch(a.err, errbits);
+    __syncthreads();
+    for (int c = threadIdx.x; c < K; c += BLOCK) a.cnt[(size_t)item * K + c] = s_cnt[c];
+
+    // flush the LDS boxes into the global arrays
+    const int64_t NC = a.NC;
+    for (int c = threadIdx.x; c < G::NFF; c += BLOCK) {
+        int lx, ly, lz;
+        G::coords(c + G::FOFF, lx, ly, lz);
+        bool in = lx >= -1 && lx <= sx && ly >= -1 && ly <= sy && (NDIM == 2 || (lz >= -1 && lz <= sz));
+        if (!in) continue;
+        int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned long long val = Dc[q * G::NFF + c];
+            if (val) atomicAdd((unsigned long long*)&a.Dcorr[q * NC + g], val);
+        }
+    }
+    for (int c = threadIdx.x; c < G::NP; c += BLOCK) {
+        int lx, ly, lz;
+        G::coords(c, lx, ly, lz);
+        bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
+        if (!in) continue;
+        int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned long long val = Dp[q * G::NP + c];
+            if (val) atomicAdd((unsigned long long*)&a.nJ[q * NC + g], val);
+        }
+    }
+}
+
+// Deposits amount V over a 3^NDIM stencil straight into global int64 arrays.
+template <class Pol, int NDIM>
+__device__ __forceinline__ void deposit_global(int64_t* dst, const BoxDev& bx, const int i[3],
+                                               const typename Pol::R wx[3],
+                                               const typename Pol::R wy[3],
+                                               const typename Pol::R wz[3], double V) {
+    using R = typename Pol::R;
+    int64_t tot = quant1(V);
+    int64_t acc = 0;
+    const int zlo = NDIM == 3 ? 0 : 1, zhi = NDIM == 3 ? 2 : 1;
+    int64_t centre = 0;
+    for (int oz = zlo; oz <= zhi; ++oz)
+        for (int oy = 0; oy < 3; ++oy)
+            for (int ox = 0; ox < 3; ++ox) {
+                int64_t g = global_cell<NDIM>(bx, i[0] + ox - 1, i[1] + oy - 1, i[2] + oz - 1);
+                if (ox == 1 && oy == 1 && oz == 1) {
+                    centre = g;
+                    continue;
+                }
+                R wxy = wx[ox] * wy[oy];
+                double W = (double)(NDIM == 3 ? wxy * wz[oz] : wxy);
+                int64_t q = quant(W, V);
+                acc += q;
+                atomicAdd((unsigned long long*)&dst[g], (unsigned long long)q);
+            }
+    atomicAdd((unsigned long long*)&dst[centre], (unsigned long long)(tot - acc));
+}
+
+// n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
+// with global atomics; used once at initialisation.
+template <class Pol, int NDIM>
+__global__ void k_deposit_nJ_global(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
+                                    const BoxDev* __restrict__ boxes,
+                                    const int64_t* __restrict__ part_off, int nb, int64_t N,
+                                    uint32_t* err) {
+    using R = typename Pol::R;
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+    int i[3];
+    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+    R wx[3], wy[3], wz[3] = {R(0), R(1), R(0)};
+    Pol::weights(P.d[0][j], wx);
+    Pol::weights(P.d[1][j], wy);
+    if (NDIM == 3) Pol::weights(P.d[2][j], wz);
+    R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
+    typename Pol::K k = Pol::kin(v, bx.C, bx.C2, bx.iC);
+    double qmm = (double)P.qm[j] * (double)P.m[j];
+    double V[4] = {qmm * bx.S, (qmm * (double)k.u[0]) * bx.S, (qmm * (double)k.u[1]) * bx.S,
+                   (qmm * (double)k.u[2]) * bx.S};
+    for (int c = 0; c < 4; ++c) {
+        if (!(fabs(V[c]) < kMaxAmount)) {
+            latch(err, ERRBIT_RANGE);
+            continue;
+        }
+        deposit_global<Pol, NDIM>(nJ + c * NC, bx, i, wx, wy, wz, V[c]);
+    }
+}
+
+}  // namespace mhdpic

@@ -14,7 +14,8 @@ from typing import Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmhdpic.so")
+# MHDPIC_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("MHDPIC_LIB") or os.path.join(HERE, "libmhdpic.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
@@ -22,7 +23,7 @@ FP64, FP32_MIXED = 0, 1
 EXPORTED = [
     "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
-    "mhdpic_selftest_arith",
+    "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
 ]
 
 
@@ -68,6 +69,10 @@ def lib():
         L.mhdpic_destroy.argtypes = [vp]
         L.mhdpic_last_error.restype = ct.c_char_p
         L.mhdpic_last_error.argtypes = []
+        L.mhdpic_timing_enable.restype = ct.c_int
+        L.mhdpic_timing_enable.argtypes = [vp, ct.c_int32]
+        L.mhdpic_timing_read.restype = ct.c_int
+        L.mhdpic_timing_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.mhdpic_selftest_arith.restype = ct.c_int
         L.mhdpic_selftest_arith.argtypes = [vp, vp, vp, vp, ct.c_int64, vp]
         _lib = L
@@ -189,6 +194,17 @@ class Context:
         v = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
         _check(lib().mhdpic_particles_read(self._h, _ptr(x), _ptr(v), _stream(stream)))
         return x, v
+
+    def timing(self, enable: bool):
+        _check(lib().mhdpic_timing_enable(self._h, int(bool(enable))))
+
+    PHASES = ("bin", "fieldprep", "push", "clear")
+
+    def timing_read(self) -> dict:
+        ms = (ct.c_double * 4)()
+        n = (ct.c_int64 * 4)()
+        _check(lib().mhdpic_timing_read(self._h, ms, n))
+        return {p: (float(ms[k]), int(n[k])) for k, p in enumerate(self.PHASES)}
 
     def check(self, stream=None):
         _check(lib().mhdpic_check(self._h, _stream(stream)))

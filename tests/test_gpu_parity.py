@@ -213,3 +213,29 @@ def test_amount_overflow_flagged():
     with pytest.raises(M.MhdpicError) as e:
         GpuRun(wl)
     assert e.value.code == M.ERANGE
+
+
+def test_parity_sides_one_more_than_tiles():
+    # n % tile == 1 in every dimension: the last tile is shifted to two cells
+    _parity(W.gyro2d(nx=33, ny=17, ppc=4, seed=30), n_steps=4, tile=(16, 16, 1))
+    _parity(W.bell3d(n=(17, 9, 5), ppc=3, seed=31), n_steps=3, tile=(8, 4, 4))
+
+
+def test_parity_many_steps_stays_bit_exact():
+    # particles cross many tiles; binning and deposits must stay exact
+    _parity(W.shock2d(nx=256, ny=32, n_particles=256 * 32 * 4, seed=32), n_steps=24,
+            steps_per_call=8)
+
+
+def test_parity_dt_changes_between_calls():
+    _need_gpu()
+    wl = W.gyro2d(nx=20, ny=20, ppc=5, seed=33)
+    g = GpuRun(wl)
+    o = oracle_run(wl)
+    for f in (1.0, 0.5, -0.7, 1.0):
+        g.step(3, dts=[f * wl.dt])
+        o.step(wl.B, wl.vg, wl.rho, f * wl.dt, 3)
+        (D,) = g.deposits()
+        assert (D == o.D).all()
+        ((x, v),) = g.particles()
+        _assert_states(wl, o, x, v)
