@@ -139,6 +139,138 @@ def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), p
 
 
 # --------------------------------------------------------------------------
+# the two other forms
+# --------------------------------------------------------------------------
+
+def _to(dev, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _gpu_box(spec, tile=(0, 0, 0)):
+    from paper_1412_1087_amd import mhdpic as M
+    return M.Box(ndim=spec.ndim, n=spec.n, dx=spec.dx, x0=spec.x0, C=spec.C,
+                 qomc_gas=spec.qomc_gas, hall=spec.hall, frac_bits=spec.frac_bits,
+                 max_move_cells=spec.max_move_cells, tile=tile)
+
+
+def _time_steps(ctx, B, vg, rho, dt, steps, warmup):
+    import torch
+    ctx.step(B, vg, rho, dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.step(B, vg, rho, dt, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    return e0.elapsed_time(e1)
+
+
+def run_precision_form(steps: int, warmup: int):
+    """Precision form on the 128^3, 32-per-cell beam box, against the binary64
+    path on the same seed: throughput of both and the one-step error."""
+    import torch
+    from paper_1412_1087_amd import mhdpic as M
+    from paper_1412_1087_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wl = W.bell3d(n=128, ppc=32, seed=4001, n_steps=100)
+    label = "bell3d-128^3-ppc32-hall"
+    box = _gpu_box(wl.box)
+    B, vg, rho = _to(dev, wl.B), _to(dev, wl.vg), _to(dev, wl.rho)
+    x, v, m, qm = (_to(dev, a) for a in (wl.x, wl.v, wl.m, wl.qm))
+    out = {"workload": label, "particles": wl.N, "cells": box.n_cells, "steps": steps}
+    ctx64 = M.Context([box], [wl.N], x, v, m, qm, precision=M.FP64)
+    ctx32 = M.Context([box], [wl.N], x, v, m, qm, precision=M.FP32_MIXED)
+    del x, v, m, qm
+    # one step from the same state: error of the precision form
+    ctx64.step(B, vg, rho, wl.dt, 1)
+    ctx32.step(B, vg, rho, wl.dt, 1)
+    x64, v64 = ctx64.particles_read()
+    x32, v32 = ctx32.particles_read()
+    D64 = ctx64.deposit_read()
+    D32 = ctx32.deposit_read()
+    torch.cuda.synchronize()
+    Lb = torch.tensor([128.0, 128.0, 128.0], device=dev, dtype=torch.float64)[:, None]
+    dx = x32 - x64
+    dx = dx - Lb * torch.round(dx / Lb)
+    vmax = v64.abs().max().item()
+    err = {"pos_max_abs_cells": dx.abs().max().item(),
+           "v_max_abs_rel": ((v32 - v64).abs().max().item()) / vmax}
+    names = ["n", "Jx", "Jy", "Jz", "-dMx", "-dMy", "-dMz", "-dEk"]
+    for ch, nm in enumerate(names):
+        a = D64[ch].double()
+        err[f"dep_{nm}_max_abs_rel"] = ((D32[ch].double() - a).abs().max() /
+                                        a.abs().max().clamp(min=1)).item()
+    out["one_step_error_vs_fp64"] = err
+    del x64, v64, x32, v32, D64, D32
+    ms64 = _time_steps(ctx64, B, vg, rho, wl.dt, steps, warmup)
+    ctx64.destroy()
+    del ctx64
+    torch.cuda.empty_cache()
+    ms32 = _time_steps(ctx32, B, vg, rho, wl.dt, steps, warmup)
+    ctx32.destroy()
+    out["fp64_value"] = round(wl.N * steps / (ms64 * 1e-3), 1)
+    out["value"] = round(wl.N * steps / (ms32 * 1e-3), 1)
+    out["speedup_vs_fp64"] = round(ms64 / ms32, 3)
+    alg = algorithmic_bytes(3, wl.N, box.n_cells, fsz=4, msz=4)
+    out["hbm_frac_whole_step"] = round(alg["per_launch"] / (ms32 * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)
+    log(f"precision form: fp32 {out['value']:.4g}/s, fp64 {out['fp64_value']:.4g}/s, err {err}")
+    return out
+
+
+def run_batched_form(steps: int):
+    """256 independent 2D boxes (sides log-uniform in 16..128, 4..64 per cell),
+    tile picked by the library autotuner, steps run as one HIP graph launch;
+    precision form, with the binary64 path on the same boxes for comparison."""
+    import torch
+    from paper_1412_1087_amd import mhdpic as M
+    from paper_1412_1087_amd import workloads as W
+    dev = torch.device("cuda:0")
+    wls = W.batch2d(n_boxes=256, seed0=5000, n_steps=100)
+    N = sum(w.N for w in wls)
+    NC = sum(w.box.n_cells for w in wls)
+    cat = lambda f: np.concatenate([f(w) for w in wls], axis=-1)
+    B, vg, rho = _to(dev, cat(lambda w: w.B)), _to(dev, cat(lambda w: w.vg)), _to(dev, cat(lambda w: w.rho))
+    x, v = _to(dev, cat(lambda w: w.x)), _to(dev, cat(lambda w: w.v))
+    m, qm = _to(dev, cat(lambda w: w.m)), _to(dev, cat(lambda w: w.qm))
+    dts = [w.dt for w in wls]
+    nps = [w.N for w in wls]
+    out = {"workload": "batch2d-256-boxes", "boxes": len(wls), "particles": N, "cells": NC,
+           "steps": steps}
+    res = {}
+    for prec, name in ((M.FP32_MIXED, "fp32"), (M.FP64, "fp64")):
+        boxes0 = [_gpu_box(w.box) for w in wls]
+        tile, tms = M.autotune(boxes0, nps, x, v, m, qm, B, vg, rho, dts, n_steps=10, precision=prec)
+        boxes = [_gpu_box(w.box, tile) for w in wls]
+        ctx = M.Context(boxes, nps, x, v, m, qm, precision=prec)
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        ctx.step_graph(B, vg, rho, dts, steps, stream)  # capture + first launch
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step_graph(B, vg, rho, dts, steps, stream)
+        e1.record(stream)
+        stream.synchronize()
+        ctx.check(stream)
+        ms = e0.elapsed_time(e1)
+        res[name] = dict(value=round(N * steps / (ms * 1e-3), 1), tile=list(tile),
+                         ms_per_step=round(ms / steps, 5))
+        ctx.destroy()
+        log(f"batched {name}: tile {tile}, {res[name]['value']:.4g}/s")
+    out["value"] = res["fp32"]["value"]
+    out["tile"] = res["fp32"]["tile"]
+    out["fp64_value"] = res["fp64"]["value"]
+    out["fp64_tile"] = res["fp64"]["tile"]
+    out["speedup_vs_fp64"] = round(res["fp32"]["value"] / res["fp64"]["value"], 3)
+    out["launch"] = "one hipGraph launch per call of %d steps" % steps
+    return out
+
+
+# --------------------------------------------------------------------------
 # CPU baseline: the oracle on a bounded sample
 # --------------------------------------------------------------------------
 
@@ -183,6 +315,8 @@ def main():
     ap.add_argument("--workload", default="bell3d")
     ap.add_argument("--tile", default="0,0,0")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision-form and batched-form legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +341,11 @@ def main():
                     kernel="k_push_f64", avg_launch_us=round(push_avg_s * 1e6, 2),
                     alg_bytes_per_launch=alg["per_launch"],
                     alg_bytes_per_particle=alg["per_particle"], alg_bytes_per_cell=alg["per_cell"])
+    forms = None
+    if not args.no_forms:
+        import torch
+        torch.cuda.empty_cache()
+        forms = {"fp32_mixed": run_precision_form(100, 5), "batched": run_batched_form(100)}
     cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     phases = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in g["phases"].items()}
     out = {
@@ -228,6 +367,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms": phases,
+        "forms": forms,
         "hbm_frac_whole_step": round(
             (alg["per_launch"] / (ms * 1e-3 / args.steps)) / 1e9 / HBM_PEAK_GBS, 4),
         "checksum": g["checksum"],

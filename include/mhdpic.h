@@ -108,6 +108,9 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
                 mhdpic_ctx** out);
 
 /* Advances all particles n_steps steps (App. A.2, A.3) through fixed fields.
+ * Waits for the stream only when dt differs from the previous call (the new
+ * step constants are uploaded).  The call may be captured into a HIP graph if
+ * dt equals the previous call's (see also mhdpic_step_graph).
  *   B, vg  device, [3][cells] doubles: cell-centred magnetic field and gas velocity
  *   rho    device, [cells] doubles: gas density (read only where hall = 1)
  *   dt     host, [n_boxes] doubles: time step of each box (may be negative)
@@ -117,6 +120,32 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
  * C*|dt|/dx > max_move_cells for any box.  Does not wait for the stream. */
 int mhdpic_step(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
                 const double* dt, int32_t n_steps, void* hip_stream);
+
+/* mhdpic_step through a HIP graph.  The first call (and any call whose
+ * B, vg, rho, dt or n_steps differ from the cached ones) captures the n_steps
+ * steps into a graph owned by the context; every call then launches that
+ * graph, so one launch advances all boxes n_steps steps.  n_steps must be even
+ * (the step's buffer swaps then return to the captured state after each
+ * launch) and hip_stream must not be the default stream.  Waits for the stream
+ * when it captures.  Does not wait otherwise. */
+int mhdpic_step_graph(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
+                      const double* dt, int32_t n_steps, void* hip_stream);
+
+/* Picks the tile shape (cells per tile, the LDS staging unit of the push
+ * kernel) with the shortest step time for this workload: for every compiled
+ * shape it builds a context in `workspace` from the given particles, runs two
+ * warm-up steps and times n_steps steps with HIP events.  Arguments as for
+ * mhdpic_init and mhdpic_step (the particle arrays are read, not changed);
+ * workspace needs mhdpic_autotune_workspace_size bytes.  Writes the shape to
+ * tile_out[3] (use it as mhdpic_box.tile) and, if not NULL, its time per step
+ * in ms.  Waits for the stream. */
+int mhdpic_autotune_workspace_size(const mhdpic_box* boxes, int32_t n_boxes,
+                                   const int64_t* n_particles, int32_t precision, size_t* bytes);
+int mhdpic_autotune(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                    int32_t precision, const double* x, const double* v, const double* m,
+                    const double* qm, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps, void* workspace, size_t ws_bytes,
+                    void* hip_stream, int32_t* tile_out, double* ms_per_step);
 
 /* Copies the deposits to out (device, [8][cells] int64): channels
  * 0..3 = n_CR, J_CR x,y,z at the current positions; 4..6 = accumulated

@@ -51,7 +51,19 @@ struct TileShape {
     int x, y, z;
 };
 
-bool tile_supported(int ndim, int prec, const TileShape& t) {
+constexpr size_t kLdsPerCU = 160 * 1024;
+
+// LDS bytes of the push kernel for a tile shape (the kernel's Geo layout).
+size_t push_lds_bytes(int ndim, int prec, const TileShape& t) {
+    size_t PX = t.x + 4, PY = t.y + 4, PZ = ndim == 3 ? t.z + 4 : 1;
+    size_t NP = PX * PY * PZ;
+    size_t FOFF = ndim == 3 ? PX * PY : PX;
+    size_t NFF = NP - 2 * FOFF;
+    size_t fsz = prec == MHDPIC_FP64 ? 8 : 4;
+    return NFF * 4 * 8 + NP * 4 * 8 + NFF * 6 * fsz;
+}
+
+bool tile_compiled(int ndim, const TileShape& t) {
     if (ndim == 2) {
         return (t.x == 16 && t.y == 16) || (t.x == 32 && t.y == 16) || (t.x == 8 && t.y == 8) ||
                (t.x == 32 && t.y == 32) || (t.x == 64 && t.y == 16);
@@ -59,7 +71,10 @@ bool tile_supported(int ndim, int prec, const TileShape& t) {
     return (t.x == 8 && t.y == 4 && t.z == 4) || (t.x == 8 && t.y == 8 && t.z == 4) ||
            (t.x == 4 && t.y == 4 && t.z == 4) || (t.x == 8 && t.y == 8 && t.z == 8) ||
            (t.x == 16 && t.y == 4 && t.z == 4);
-    (void)prec;
+}
+
+bool tile_supported(int ndim, int prec, const TileShape& t) {
+    return tile_compiled(ndim, t) && push_lds_bytes(ndim, prec, t) <= kLdsPerCU;
 }
 
 TileShape default_tile(int ndim, int prec) {
@@ -81,6 +96,17 @@ struct Layout {
     int K = 27;
     size_t boxes = 0, part_off = 0, cell_off = 0;
     size_t total = 0;
+};
+
+struct GraphKey {
+    const double* B = nullptr;
+    const double* vg = nullptr;
+    const double* rho = nullptr;
+    int32_t n_steps = 0;
+    std::vector<double> dt;
+    bool operator==(const GraphKey& o) const {
+        return B == o.B && vg == o.vg && rho == o.rho && n_steps == o.n_steps && dt == o.dt;
+    }
 };
 
 }  // namespace
@@ -108,6 +134,10 @@ struct mhdpic_ctx {
     };
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
+    bool dt_uploaded = false;
+    // cached graph of mhdpic_step_graph
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
 };
 
 namespace {
@@ -122,7 +152,7 @@ int validate_boxes(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     tile = {boxes[0].tile[0], boxes[0].tile[1], ndim == 3 ? boxes[0].tile[2] : 1};
     if (tile.x == 0 && tile.y == 0) tile = default_tile(ndim, precision);
     if (!tile_supported(ndim, precision, tile))
-        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");
+        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel or exceeds the LDS");
     int64_t N = 0, NC = 0;
     for (int b = 0; b < nb; ++b) {
         const mhdpic_box& B = boxes[b];
@@ -474,6 +504,88 @@ int post_error_copy(mhdpic_ctx* c, hipStream_t s) {
     return MHDPIC_OK;
 }
 
+int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    if (!dt || n_steps < 0) return fail(MHDPIC_EINVAL, "dt is NULL or n_steps < 0");
+    if (c->L.NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
+    bool any_hall = false;
+    for (auto& b : c->boxes) any_hall |= b.hall != 0;
+    if (any_hall && !rho) return fail(MHDPIC_EINVAL, "rho is NULL with hall = 1");
+    for (int b = 0; b < c->nb; ++b) {
+        const mhdpic_box& bx = c->boxes[b];
+        if (!std::isfinite(dt[b])) return fail(MHDPIC_EINVAL, "dt must be finite");
+        for (int d = 0; d < c->ndim; ++d) {
+            double cells = bx.C * std::fabs(dt[b]) / bx.dx[d];
+            if (!(cells <= bx.max_move_cells * (1.0 - 1e-12)))
+                return fail(MHDPIC_ERANGE, "C*|dt|/dx exceeds max_move_cells");
+        }
+    }
+    return MHDPIC_OK;
+}
+
+// Refreshes the per-call step constants on the device when dt changed.  A
+// stream being captured cannot take the upload (it would be replayed from
+// host memory): dt must then already be current.
+int set_dt(mhdpic_ctx* c, const double* dt, hipStream_t s, bool capturing) {
+    bool changed = !c->dt_uploaded;
+    for (int b = 0; b < c->nb && !changed; ++b) changed = c->bdev[b].dt != dt[b];
+    if (!changed) return MHDPIC_OK;
+    if (capturing)
+        return fail(MHDPIC_EINVAL, "dt differs from the last call: step once before capturing");
+    for (int b = 0; b < c->nb; ++b) {
+        BoxDev& d = c->bdev[b];
+        d.dt = dt[b];
+        d.hdt = 0.5 * dt[b];
+        for (int k = 0; k < 3; ++k) d.hdx[k] = k < c->ndim ? d.hdt / c->boxes[b].dx[k] : 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host copy may change after return
+    c->dt_uploaded = true;
+    return MHDPIC_OK;
+}
+
+// The kernels of n_steps steps: re-binning for this call's dt, then per step
+// field preparation, the push and (except after the last) re-binning.
+int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                  int32_t n_steps, hipStream_t s, bool allow_timing) {
+    if (!rho) rho = B;  // never read without the Hall term
+    const bool saved = c->timing;
+    c->timing = c->timing && allow_timing;
+    int rc;
+    {
+        PhaseTimer t(c, s, 0);
+        rc = launch_bin_any(c, s, true);
+    }
+    for (int st = 0; st < n_steps && !rc; ++st) {
+        {
+            PhaseTimer t(c, s, 1);
+            rc = launch_fieldprep(c, B, vg, rho, s);
+        }
+        if (rc) break;
+        {
+            PhaseTimer t(c, s, 3);
+            int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
+            fill_i64(next, 4 * c->L.NC, s);
+        }
+        {
+            PhaseTimer t(c, s, 2);
+            rc = launch_push(c, s);
+        }
+        if (rc) break;
+        c->nj = 1 - c->nj;
+        if (st + 1 < n_steps) {
+            PhaseTimer t(c, s, 0);
+            rc = launch_bin_any(c, s, false);
+        }
+    }
+    c->timing = saved;
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return MHDPIC_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -654,65 +766,145 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
 
 int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
                 const double* dt, int32_t n_steps, void* hip_stream) {
-    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
-    if (!dt || n_steps < 0) return fail(MHDPIC_EINVAL, "dt is NULL or n_steps < 0");
-    if (c->L.NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
-    bool any_hall = false;
-    for (auto& b : c->boxes) any_hall |= b.hall != 0;
-    if (any_hall && !rho) return fail(MHDPIC_EINVAL, "rho is NULL with hall = 1");
-    int rc = poll_error(c);
+    int rc = check_step_args(c, B, vg, rho, dt, n_steps);
     if (rc) return rc;
-    for (int b = 0; b < c->nb; ++b) {
-        const mhdpic_box& bx = c->boxes[b];
-        if (!std::isfinite(dt[b])) return fail(MHDPIC_EINVAL, "dt must be finite");
-        for (int d = 0; d < c->ndim; ++d) {
-            double cells = bx.C * std::fabs(dt[b]) / bx.dx[d];
-            if (!(cells <= bx.max_move_cells * (1.0 - 1e-12)))
-                return fail(MHDPIC_ERANGE, "C*|dt|/dx exceeds max_move_cells");
-        }
-    }
+    rc = poll_error(c);
+    if (rc) return rc;
     if (n_steps == 0) return MHDPIC_OK;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
     c->last_stream = s;
-    for (int b = 0; b < c->nb; ++b) {
-        BoxDev& d = c->bdev[b];
-        d.dt = dt[b];
-        d.hdt = 0.5 * dt[b];
-        for (int k = 0; k < 3; ++k) d.hdx[k] = k < c->ndim ? d.hdt / c->boxes[b].dx[k] : 0.0;
-    }
-    HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
-                           hipMemcpyHostToDevice, s));
-    if (!rho) rho = B;  // never read without the Hall term
-    {
-        PhaseTimer t(c, s, 0);
-        rc = launch_bin_any(c, s, true);
-    }
+    rc = set_dt(c, dt, s, capturing);
     if (rc) return rc;
-    for (int st = 0; st < n_steps; ++st) {
-        {
-            PhaseTimer t(c, s, 1);
-            rc = launch_fieldprep(c, B, vg, rho, s);
+    rc = enqueue_steps(c, B, vg, rho, n_steps, s, !capturing);
+    if (rc) return rc;
+    if (capturing) return MHDPIC_OK;
+    return post_error_copy(c, s);
+}
+
+int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                      const double* dt, int32_t n_steps, void* hip_stream) {
+    int rc = check_step_args(c, B, vg, rho, dt, n_steps);
+    if (rc) return rc;
+    if (n_steps <= 0 || n_steps % 2) return fail(MHDPIC_EINVAL, "n_steps must be even and > 0");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (!s) return fail(MHDPIC_EINVAL, "graph capture needs a non-default stream");
+    rc = poll_error(c);
+    if (rc) return rc;
+    c->last_stream = s;
+    GraphKey key{B, vg, rho, n_steps, std::vector<double>(dt, dt + c->nb)};
+    if (!c->graph_exec || !(c->graph_key == key)) {
+        if (c->graph_exec) {
+            HIP_TRY(hipGraphExecDestroy(c->graph_exec));
+            c->graph_exec = nullptr;
         }
+        rc = set_dt(c, dt, s, false);  // uploads happen outside the graph
         if (rc) return rc;
-        {
-            PhaseTimer t(c, s, 3);
-            int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
-            fill_i64(next, 4 * c->L.NC, s);
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_steps(c, B, vg, rho, n_steps, s, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
         }
-        {
-            PhaseTimer t(c, s, 2);
-            rc = launch_push(c, s);
+        if (e != hipSuccess) return fail(MHDPIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph_exec = nullptr;
+            return fail(MHDPIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
+        c->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+    return post_error_copy(c, s);
+}
+
+namespace {
+
+std::vector<TileShape> tile_candidates(int ndim, int prec) {
+    std::vector<TileShape> all = ndim == 2
+        ? std::vector<TileShape>{{16, 16, 1}, {32, 16, 1}, {8, 8, 1}, {32, 32, 1}, {64, 16, 1}}
+        : std::vector<TileShape>{{8, 4, 4}, {8, 8, 4}, {4, 4, 4}, {8, 8, 8}, {16, 4, 4}};
+    std::vector<TileShape> ok;
+    for (const TileShape& t : all)
+        if (tile_supported(ndim, prec, t)) ok.push_back(t);
+    return ok;
+}
+
+std::vector<mhdpic_box> with_tile(const mhdpic_box* boxes, int32_t nb, const TileShape& t) {
+    std::vector<mhdpic_box> v(boxes, boxes + nb);
+    for (auto& b : v) {
+        b.tile[0] = t.x;
+        b.tile[1] = t.y;
+        b.tile[2] = b.ndim == 3 ? t.z : 1;
+    }
+    return v;
+}
+
+}  // namespace
+
+int mhdpic_autotune_workspace_size(const mhdpic_box* boxes, int32_t n_boxes,
+                                   const int64_t* n_particles, int32_t precision, size_t* bytes) {
+    if (!bytes || !boxes || n_boxes < 1) return fail(MHDPIC_EINVAL, "NULL argument");
+    size_t best = 0;
+    for (const TileShape& t : tile_candidates(boxes[0].ndim, precision)) {
+        std::vector<mhdpic_box> b = with_tile(boxes, n_boxes, t);
+        size_t sz = 0;
+        int rc = mhdpic_workspace_size(b.data(), n_boxes, n_particles, precision, &sz);
         if (rc) return rc;
-        c->nj = 1 - c->nj;
-        if (st + 1 < n_steps) {
-            PhaseTimer t(c, s, 0);
-            rc = launch_bin_any(c, s, false);
-            if (rc) return rc;
+        best = std::max(best, sz);
+    }
+    *bytes = best;
+    return MHDPIC_OK;
+}
+
+int mhdpic_autotune(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                    int32_t precision, const double* x, const double* v, const double* m,
+                    const double* qm, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps, void* workspace, size_t ws_bytes,
+                    void* hip_stream, int32_t* tile_out, double* ms_per_step) {
+    if (!boxes || n_boxes < 1 || !tile_out || n_steps < 1)
+        return fail(MHDPIC_EINVAL, "NULL argument or n_steps < 1");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    TileShape best{0, 0, 0};
+    int rc = MHDPIC_OK;
+    for (const TileShape& t : tile_candidates(boxes[0].ndim, precision)) {
+        std::vector<mhdpic_box> b = with_tile(boxes, n_boxes, t);
+        mhdpic_ctx* c = nullptr;
+        rc = mhdpic_init(b.data(), n_boxes, n_particles, precision, x, v, m, qm, workspace, ws_bytes,
+                         hip_stream, &c);
+        if (rc) break;
+        rc = mhdpic_step(c, B, vg, rho, dt, 2, hip_stream);  // warm-up, uploads dt
+        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventRecord");
+        if (!rc) rc = mhdpic_step(c, B, vg, rho, dt, n_steps, hip_stream);
+        if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventRecord");
+        float ms = 0.0f;
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventSynchronize");
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventElapsedTime");
+        if (!rc) rc = mhdpic_check(c, hip_stream);
+        mhdpic_destroy(c);
+        if (rc) break;
+        if (best.x == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = t;
         }
     }
-    HIP_TRY(hipGetLastError());
-    return post_error_copy(c, s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    tile_out[0] = best.x;
+    tile_out[1] = best.y;
+    tile_out[2] = best.z;
+    if (ms_per_step) *ms_per_step = best_ms / n_steps;
+    return MHDPIC_OK;
 }
 
 int mhdpic_deposit_read(mhdpic_ctx* c, int64_t* out, int32_t reset_accumulated, void* hip_stream) {
@@ -794,6 +986,10 @@ int mhdpic_timing_read(mhdpic_ctx* c, double* ms, int64_t* launches) {
 
 int mhdpic_destroy(mhdpic_ctx* c) {
     if (!c) return MHDPIC_OK;
+    if (c->graph_exec) {
+        if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+        (void)hipGraphExecDestroy(c->graph_exec);
+    }
     for (auto& mk : c->marks) {
         (void)hipEventSynchronize(mk.b);
         c->pool.push_back(mk.a);

@@ -24,6 +24,7 @@ EXPORTED = [
     "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
+    "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune",
 ]
 
 
@@ -73,6 +74,17 @@ def lib():
         L.mhdpic_timing_enable.argtypes = [vp, ct.c_int32]
         L.mhdpic_timing_read.restype = ct.c_int
         L.mhdpic_timing_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
+        L.mhdpic_step_graph.restype = ct.c_int
+        L.mhdpic_step_graph.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32, vp]
+        L.mhdpic_autotune_workspace_size.restype = ct.c_int
+        L.mhdpic_autotune_workspace_size.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32,
+                                                     ct.POINTER(ct.c_int64), ct.c_int32,
+                                                     ct.POINTER(sz)]
+        L.mhdpic_autotune.restype = ct.c_int
+        L.mhdpic_autotune.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32, ct.POINTER(ct.c_int64),
+                                      ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                      ct.POINTER(ct.c_double), ct.c_int32, vp, sz, vp,
+                                      ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
         L.mhdpic_selftest_arith.restype = ct.c_int
         L.mhdpic_selftest_arith.argtypes = [vp, vp, vp, vp, ct.c_int64, vp]
         _lib = L
@@ -181,6 +193,15 @@ class Context:
         _check(lib().mhdpic_step(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
                                  _stream(stream)))
 
+    def step_graph(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor | None, dt,
+                   n_steps: int, stream):
+        """n_steps (even) steps as one cached HIP graph launch on a non-default stream."""
+        if isinstance(dt, (int, float)):
+            dt = [float(dt)] * len(self.boxes)
+        dts = (ct.c_double * len(self.boxes))(*[float(a) for a in dt])
+        _check(lib().mhdpic_step_graph(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                       _stream(stream)))
+
     def deposit_read(self, reset_accumulated: bool = False, out: torch.Tensor | None = None,
                      stream=None) -> torch.Tensor:
         if out is None:
@@ -219,6 +240,27 @@ class Context:
             self.destroy()
         except Exception:
             pass
+
+
+def autotune(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg, rho, dt,
+             n_steps: int = 10, precision: int = FP64, stream=None):
+    """Tile shape with the shortest measured step for this workload (library autotuner)."""
+    arr = _boxes_array(boxes)
+    npart = (ct.c_int64 * len(boxes))(*[int(a) for a in n_particles])
+    size = ct.c_size_t()
+    _check(lib().mhdpic_autotune_workspace_size(arr, len(boxes), npart, int(precision),
+                                                ct.byref(size)))
+    ws = torch.empty(max(int(size.value), 256), dtype=torch.uint8, device=x.device)
+    if isinstance(dt, (int, float)):
+        dt = [float(dt)] * len(boxes)
+    dts = (ct.c_double * len(boxes))(*[float(a) for a in dt])
+    tile = (ct.c_int32 * 3)()
+    ms = ct.c_double()
+    _check(lib().mhdpic_autotune(arr, len(boxes), npart, int(precision), _ptr(x), _ptr(v), _ptr(m),
+                                 _ptr(qm), _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                 _ptr(ws), int(size.value), _stream(stream), tile, ct.byref(ms)))
+    del ws
+    return (int(tile[0]), int(tile[1]), int(tile[2])), float(ms.value)
 
 
 def selftest_arith(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:

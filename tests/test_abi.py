@@ -100,3 +100,12 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.mhdpic_check(None, None) == M.EINVAL
     assert lib.mhdpic_destroy(None) == M.OK
     assert b"NULL" in lib.mhdpic_last_error()
+
+
+def test_tile_shapes_that_exceed_the_lds_are_rejected(lib):
+    from paper_1412_1087_amd import mhdpic as M
+    b = M.Box(ndim=3, n=(16, 16, 16), tile=(8, 8, 8))
+    with pytest.raises(M.MhdpicError) as e:
+        M.workspace_size([b], [100], M.FP64)  # 170 KB of LDS in binary64
+    assert e.value.code == M.ENOTSUP
+    assert M.workspace_size([b], [100], M.FP32_MIXED) > 0
