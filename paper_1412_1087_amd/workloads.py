@@ -7,7 +7,7 @@ GPU library's tests and the oracle's tests take their inputs from here, so
 both sides see the same bits.
 
 Units are the paper's code units: rho0 = B0 = (q/mc) = 1, so the Alfven speed,
-the ion inertial length and the ion cyclotron frequency are all 1 (Sec. 5.1).
+the ion inertial length and the ion cyclotron frequency are all 1 (Sec. 5).
 Cells are one ion inertial length wide.
 
 Workloads (sizes are parameters so that tests can shrink them):
