@@ -20,19 +20,23 @@ namespace mhdpic {
 // operations of the step kernel of the precision form.
 template <class Pol, int NDIM>
 __device__ __forceinline__ void half_step_cell(const typename Pol::Part& P, int j, const BoxDev& bx,
-                                               int i[3]) {
+                                               int i[3], int& cls) {
     using R = typename Pol::R;
     unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
     R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
     typename Pol::K kn = Pol::kin(v, bx.C, bx.C2, bx.iC);
+    int s[3] = {0, 0, 0};
     for (int d = 0; d < NDIM; ++d) {
         R dl = P.d[d][j];
-        i[d] = wrap_shift(i[d], Pol::drift(dl, kn.u[d], Pol::hdx(bx.hdx[d])), bx.n[d]);
+        const R h = Pol::hdx(bx.hdx[d]);
+        i[d] = wrap_shift(i[d], Pol::drift(dl, kn.u[d], h), bx.n[d]);
+        s[d] = Pol::drift(dl, kn.u[d], h);  // predicted second half drift
     }
+    cls = shift_class<NDIM>(s[0], s[1], s[2]);
 }
 
-// Codes (and bank residues) for this call's dt; the push computes them for
-// the later steps of the call.
+// Code words for this call's dt; the push computes them for the later steps
+// of the call.
 template <class Pol, int NDIM>
 __global__ void __launch_bounds__(256)
 k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __restrict__ cnt,
@@ -50,10 +54,10 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     __syncthreads();
     uint32_t errbits = 0;
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
-        int i[3];
-        half_step_cell<Pol, NDIM>(P, j, bx, i);
+        int i[3], cls;
+        half_step_cell<Pol, NDIM>(P, j, bx, i, cls);
         int k = move_code<NDIM>(bx, T, tx, ty, tz, i, errbits);
-        code[j] = (uint16_t)(k | (bank_residue<NDIM>(bx, T, tx, ty, tz, k, i) << 5));
+        code[j] = pack_code(k, bank_residue<NDIM>(bx, T, tx, ty, tz, k, i), cls);
         atomicAdd(&s_cnt[k], 1u);
     }
     if (errbits) latch(err, errbits);
@@ -166,16 +170,146 @@ __global__ void k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* 
     }
 }
 
-// Moves the particles of each current work item to their groups' offsets.
-// The item is moved in chunks of one particle per thread.  Within a chunk,
-// each group's particles are laid out level by level: level r holds the r-th
-// particle of every bank residue present, in residue order, so consecutive
-// particles (and lanes of the next push) fall on distinct LDS bank pairs while
-// the stores of a chunk stay within a window of the chunk's size.
+// One particle's record, held in registers while it is moved.
+template <int NDIM, typename PS>
+struct Rec {
+    using R = typename PS::R;
+    uint32_t cell;
+    R d[NDIM];
+    R v[3];
+    R m, qm;
+    int32_t pid;
+    __device__ __forceinline__ void load(const PS& A, int j) {
+        cell = A.cell[j];
+#pragma unroll
+        for (int q = 0; q < NDIM; ++q) d[q] = A.d[q][j];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] = A.v[q][j];
+        m = A.m[j];
+        qm = A.qm[j];
+        pid = A.pid[j];
+    }
+    __device__ __forceinline__ void store(const PS& B, uint32_t s) const {
+        B.cell[s] = cell;
+#pragma unroll
+        for (int q = 0; q < NDIM; ++q) B.d[q][s] = d[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) B.v[q][s] = v[q];
+        B.m[s] = m;
+        B.qm[s] = qm;
+        B.pid[s] = pid;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restrict__ dst,
+                                           const uint16_t* from, const uint32_t* to, int begin,
+                                           int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[to[i]] = src[begin + from[i]];
+}
+
+// Moves the particles of each current work item to their groups' offsets
+// (3D; the 2D binning uses k_bin_scatter_chunk).
+//
+// Order within a group (the particles of one item with one direction code):
+// the particles that stay in the tile are grouped by the class of their
+// predicted predictor shift, and each class, like each moving group, is laid
+// out level by level: level r holds the r-th particle of every bank residue
+// present, in residue order.  Sixteen consecutive particles of a level have
+// distinct residues at their next half-step cell and, sharing one shift, at
+// their predictor cell too, so the lanes of the next push fall on distinct
+// LDS bank pairs in both deposits.
+//
+// Pass 1 ranks every particle within its (group, residue) by an LDS counter;
+// pass 2 turns the ranks into an LDS map from destination to source, and the
+// particles are moved one array at a time in destination order.
 template <int NDIM, typename PS, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_bin_scatter(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
-              const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
+k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
+                    const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
+    constexpr int K = Codes<NDIM>::K;
+    constexpr int STAY = Codes<NDIM>::STAY;
+    constexpr int NCL = K;        // shift classes (3^NDIM)
+    constexpr int NG = NCL + K;   // groups: stay classes, then moving codes
+    constexpr int RS = kResidues;
+    __shared__ uint32_t s_n[NG * RS];
+    __shared__ uint32_t s_base[NG], s_lbase[NG];
+    __shared__ uint32_t s_key[kItemParticles];
+    __shared__ uint16_t s_src[kItemParticles];
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    if (w.end - w.begin > kItemParticles) return;  // never built larger
+    for (int c = threadIdx.x; c < NG * RS; c += BLOCK) s_n[c] = 0;
+    __syncthreads();
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        const uint32_t cr = code[j];
+        const int k = code_dir(cr), b = code_residue(cr);
+        const int g = k == STAY ? code_class(cr) : NCL + k;
+        const uint32_t r = atomicAdd(&s_n[g * RS + b], 1u);
+        s_key[j - w.begin] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16);
+    }
+    __syncthreads();
+    // group bases: the stay classes in class order from the stay group's
+    // offset, the moving groups at their own offsets
+    for (int g = threadIdx.x; g < NG; g += BLOCK) {
+        uint32_t base, lb = 0;
+        for (int q = 0; q < g * RS; ++q) lb += s_n[q];
+        if (g < NCL) {
+            base = off[(size_t)item * K + STAY];
+            for (int q = 0; q < g * RS; ++q) base += s_n[q];
+        } else {
+            base = off[(size_t)item * K + (g - NCL)];
+        }
+        s_base[g] = base;
+        s_lbase[g] = lb;
+    }
+    __syncthreads();
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        const uint32_t key = s_key[j - w.begin];
+        const uint32_t r = key & 4095u;
+        const int b = (int)((key >> 12) & 15u), g = (int)(key >> 16);
+        const uint32_t* nk = s_n + g * RS;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const uint32_t nq = nk[q];
+            pos += min(nq, r) + ((q < b && nq > r) ? 1u : 0u);
+        }
+        s_src[s_lbase[g] + pos] = (uint16_t)(j - w.begin);
+    }
+    __syncthreads();
+    // destination slot of every local slot (groups in order)
+    for (int L = threadIdx.x; L < w.end - w.begin; L += BLOCK) {
+        int g = 0;
+        while (g + 1 < NG && s_lbase[g + 1] <= (uint32_t)L) ++g;
+        s_key[L] = s_base[g] + ((uint32_t)L - s_lbase[g]);
+    }
+    __syncthreads();
+    // one array at a time, in destination order
+    const int n = w.end - w.begin;
+    move_array(A.cell, Bo.cell, s_src, s_key, w.begin, n);
+#pragma unroll
+    for (int q = 0; q < NDIM; ++q) move_array(A.d[q], Bo.d[q], s_src, s_key, w.begin, n);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) move_array(A.v[q], Bo.v[q], s_src, s_key, w.begin, n);
+    move_array(A.m, Bo.m, s_src, s_key, w.begin, n);
+    move_array(A.qm, Bo.qm, s_src, s_key, w.begin, n);
+    move_array(A.pid, Bo.pid, s_src, s_key, w.begin, n);
+}
+
+// Moves the particles of each current work item to their groups' offsets
+// (2D).  The item is moved in chunks of one particle per thread.  Within a
+// chunk, each group's particles are laid out level by level (the r-th
+// particle of every bank residue present, in residue order), so 16
+// consecutive particles fall on distinct LDS bank pairs while the stores of a
+// chunk stay within a window of the chunk's size.  The next chunk's records
+// are loaded before the current chunk is stored.  In 2D the push gains less
+// from whole-group ordering than such an ordering costs in scattered stores.
+template <int NDIM, typename PS, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_bin_scatter_chunk(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
+                    const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
     constexpr int K = Codes<NDIM>::K;
     constexpr int RS = kResidues;
     __shared__ uint32_t s_n[K * RS];
@@ -186,17 +320,17 @@ k_bin_scatter(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __
     for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
     for (int c = threadIdx.x; c < K; c += BLOCK) s_run[c] = off[(size_t)item * K + c];
     __syncthreads();
+    Rec<NDIM, PS> cur;
+    uint32_t cr = 0;
+    bool act = w.begin + (int)threadIdx.x < w.end;
+    if (act) {
+        cr = code[w.begin + threadIdx.x];
+        cur.load(A, w.begin + threadIdx.x);
+    }
     for (int base = w.begin; base < w.end; base += BLOCK) {
-        const int j = base + (int)threadIdx.x;
-        const bool act = j < w.end;
-        int k = 0, b = 0;
+        const int k = code_dir(cr), b = code_residue(cr);
         uint32_t lev = 0;
-        if (act) {
-            int cr = code[j];
-            k = cr & 31;
-            b = cr >> 5;
-            lev = atomicAdd(&s_n[k * RS + b], 1u);
-        }
+        if (act) lev = atomicAdd(&s_n[k * RS + b], 1u);
         __syncthreads();
         uint32_t s = 0;
         if (act) {
@@ -219,14 +353,19 @@ k_bin_scatter(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __
         }
         __syncthreads();
         for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
-        if (act) {
-            Bo.cell[s] = A.cell[j];
-            for (int d = 0; d < NDIM; ++d) Bo.d[d][s] = A.d[d][j];
-            for (int d = 0; d < 3; ++d) Bo.v[d][s] = A.v[d][j];
-            Bo.m[s] = A.m[j];
-            Bo.qm[s] = A.qm[j];
-            Bo.pid[s] = A.pid[j];
+        // prefetch the next chunk, then store this one
+        const int jn = base + BLOCK + (int)threadIdx.x;
+        const bool actn = jn < w.end;
+        Rec<NDIM, PS> nxt;
+        uint32_t crn = 0;
+        if (actn) {
+            crn = code[jn];
+            nxt.load(A, jn);
         }
+        if (act) cur.store(Bo, s);
+        cur = nxt;
+        cr = crn;
+        act = actn;
         __syncthreads();
     }
 }

@@ -19,6 +19,7 @@ enum : uint32_t {
 constexpr double kMagic = 6755399441055744.0;
 constexpr uint32_t kMagicHi = 0x43380000u;
 constexpr double kMaxAmount = 2251799813685248.0;  // 2^51
+constexpr int kItemParticles = 4096;  // particles per work item (at most)
 
 // Box descriptor as the kernels see it.  Per-call fields (dt, hdt, hdx) are
 // refreshed by mhdpic_step before its kernels are enqueued.
@@ -46,6 +47,7 @@ struct BoxDev {
 // (2D: ix | iy<<16; 3D: ix | iy<<11 | iz<<22); d holds the offsets from the
 // cell centre in cell units; v the spatial four-velocity gamma*u.
 struct PartF64 {
+    using R = double;
     uint32_t* cell;
     double* d[3];
     double* v[3];
@@ -56,6 +58,7 @@ struct PartF64 {
 
 // Precision form: every per-particle value in single precision.
 struct PartF32 {
+    using R = float;
     uint32_t* cell;
     float* d[3];
     float* v[3];

@@ -287,6 +287,22 @@ __device__ __forceinline__ int bank_residue(const BoxDev& bx, int3 T, int tx, in
     return idx & (kResidues - 1);
 }
 
+// Code word of a particle for the binning: direction code k (bits 0-4), bank
+// residue of its next half-step cell (bits 5-8) and the class of its
+// predicted next predictor shift (bits 9-13).
+__device__ __forceinline__ uint16_t pack_code(int k, int residue, int cls) {
+    return (uint16_t)(k | (residue << 5) | (cls << 9));
+}
+__device__ __forceinline__ int code_dir(uint32_t c) { return (int)(c & 31u); }
+__device__ __forceinline__ int code_residue(uint32_t c) { return (int)((c >> 5) & 15u); }
+__device__ __forceinline__ int code_class(uint32_t c) { return (int)(c >> 9); }
+
+// Class (0 .. 3^NDIM - 1) of the cell shifts s in {-1, 0, 1} per dimension.
+template <int NDIM>
+__device__ __forceinline__ int shift_class(int s0, int s1, int s2) {
+    return NDIM == 3 ? ((s2 + 1) * 3 + (s1 + 1)) * 3 + (s0 + 1) : (s1 + 1) * 3 + (s0 + 1);
+}
+
 __device__ __forceinline__ bool item_of_block(const uint32_t* n_items, uint32_t& item) {
     const uint32_t nitems = *n_items;
     const uint32_t per_xcd = (nitems + 7u) / 8u;

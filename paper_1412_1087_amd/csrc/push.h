@@ -23,7 +23,7 @@ namespace mhdpic {
 template <class Pol>
 struct PushArgsT {
     typename Pol::Part P;        // tile-sorted particles, updated in place
-    uint16_t* code;              // out: direction code | bank residue << 5
+    uint16_t* code;              // out: code word (pack_code)
     uint32_t* cnt;               // out: [item][code] particle counts
     const typename Pol::R* EB;   // [cells][6] E and B
     int64_t* Dcorr;              // [4][cells] accumulated -dM, -dE_k
@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         ni[1] = wrap_shift(ni[1], Pol::drift(e1, k1.u[1], hy), bx.n[1]);
         if (NDIM == 3) ni[2] = wrap_shift(ni[2], Pol::drift(e2, k1.u[2], hz), bx.n[2]);
         const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits);
-        a.code[j] = (uint16_t)(k | (bank_residue<NDIM>(bx, T, tx, ty, tz, k, ni) << 5));
+        // predicted shift of the next predictor deposit (velocity as now)
+        const int p0 = Pol::drift(e0, k1.u[0], hx), p1 = Pol::drift(e1, k1.u[1], hy);
+        const int p2 = NDIM == 3 ? Pol::drift(e2, k1.u[2], hz) : 0;
+        a.code[j] = pack_code(k, bank_residue<NDIM>(bx, T, tx, ty, tz, k, ni), shift_class<NDIM>(p0, p1, p2));
         atomicAdd(&s_cnt[k], 1u);
     }
     if (errbits) latch(a.err, errbits);
