@@ -50,6 +50,14 @@ def kernel_hash() -> str:
 # workloads
 # --------------------------------------------------------------------------
 
+DATA_NOTE = {
+    "bell3d": "synthetic (seeded; shapes of the paper's Bell-instability test box)",
+    "shock2d": "synthetic (seeded; shapes of the paper's 2D shock runs: upstream/downstream "
+               "gas, CR band near the shock)",
+    "gyro2d": "synthetic (seeded; the paper's gyration-test settings on a 32x32 box)",
+}
+
+
 def make_workload(name: str):
     from paper_1412_1087_amd import workloads as W
     if name == "bell3d":
@@ -154,18 +162,61 @@ def _gpu_box(spec, tile=(0, 0, 0)):
                  max_move_cells=spec.max_move_cells, tile=tile)
 
 
-def _time_steps(ctx, B, vg, rho, dt, steps, warmup):
+def _time_steps(ctx, B, vg, rho, dt, steps, warmup, n_sub=1):
     import torch
-    ctx.step(B, vg, rho, dt, warmup)
+    ctx.step(B, vg, rho, dt, warmup, n_sub=n_sub)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    ctx.step(B, vg, rho, dt, steps)
+    ctx.step(B, vg, rho, dt, steps, n_sub=n_sub)
     e1.record()
     torch.cuda.synchronize()
     ctx.check()
     return e0.elapsed_time(e1)
+
+
+def run_subcycled_form(steps: int, warmup: int, n_sub: int = 5):
+    """Particle sub-cycling on the 64^3 beam box: steps of n_sub particle
+    sub-steps (n_CR, J_CR deposited once per step), against the same number
+    of particle steps of the same size taken one step per field update."""
+    import torch
+    from paper_1412_1087_amd import mhdpic as M
+    wl, label = make_workload("bell3d")
+    dev = torch.device("cuda:0")
+    B, vg, rho = _to(dev, wl.B), _to(dev, wl.vg), _to(dev, wl.rho)
+    ctx = M.Context([_gpu_box(wl.box)], [wl.N], *(_to(dev, a) for a in (wl.x, wl.v, wl.m, wl.qm)))
+    ms_sub = _time_steps(ctx, B, vg, rho, wl.dt * n_sub, steps, warmup, n_sub=n_sub)
+    ms_one = _time_steps(ctx, B, vg, rho, wl.dt, steps * n_sub, warmup)
+    ctx.destroy()
+    n_upd = wl.N * steps * n_sub
+    out = {"workload": label, "n_sub": n_sub, "steps": steps, "particle_step_dt": wl.dt,
+           "value": round(n_upd / (ms_sub * 1e-3), 1), "unit": "particle sub-step updates/s",
+           "nsub1_value": round(n_upd / (ms_one * 1e-3), 1),
+           "speedup_vs_nsub1": round(ms_one / ms_sub, 3)}
+    log(f"sub-cycled n_sub={n_sub}: {out['value']:.4g}/s vs {out['nsub1_value']:.4g}/s unsub-cycled")
+    return out
+
+
+def run_strip_form(steps: int, warmup: int):
+    """The FP64 path on the 2D shock-like strip (8192 x 32 cells, 16.8 M
+    particles, 80 % of them in a band of a tenth of the strip)."""
+    wl, label = make_workload("shock2d")
+    g = run_gpu(wl, steps, warmup, False)
+    alg = algorithmic_bytes(wl.box.ndim, wl.N, g["n_cells"])
+    push_ms, push_n = g["phases"]["push"]
+    push_s = push_ms * 1e-3 / max(push_n, 1)
+    out = {"workload": label, "particles": wl.N, "cells": g["n_cells"], "steps": steps,
+           "value": round(wl.N * steps / (g["ms"] * 1e-3), 1),
+           "ms_per_step": round(g["ms"] / steps, 5),
+           "push_avg_launch_us": round(push_s * 1e6, 2),
+           "push_hbm_frac": round(alg["per_launch"] / push_s / 1e9 / HBM_PEAK_GBS, 4),
+           "hbm_frac_whole_step": round(alg["per_launch"] / (g["ms"] * 1e-3 / steps) / 1e9
+                                        / HBM_PEAK_GBS, 4),
+           "phases_ms": {k: round(v[0], 3) for k, v in g["phases"].items()},
+           "traffic": load_traffic(label, alg["per_launch"])}
+    log(f"strip: {out['value']:.4g}/s, push {out['push_avg_launch_us']} us")
+    return out
 
 
 def run_precision_form(steps: int, warmup: int):
@@ -346,6 +397,10 @@ def main():
         import torch
         torch.cuda.empty_cache()
         forms = {"fp32_mixed": run_precision_form(100, 5), "batched": run_batched_form(100)}
+        torch.cuda.empty_cache()
+        forms["subcycled"] = run_subcycled_form(20, 2)
+        torch.cuda.empty_cache()
+        forms["strip2d"] = run_strip_form(20, 3)
     cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     phases = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in g["phases"].items()}
     out = {
@@ -360,7 +415,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded; shapes of the paper's Bell-instability test box)",
+        "data": DATA_NOTE.get(args.workload, "synthetic (seeded)"),
         "config": {"workload": label, "cells": g["n_cells"], "particles": N, "ndim": wl.box.ndim,
                    "hall": wl.box.hall, "C": wl.box.C, "dt": wl.dt, "tile": list(tile),
                    "precision": "fp64"},

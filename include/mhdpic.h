@@ -121,6 +121,17 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
 int mhdpic_step(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
                 const double* dt, int32_t n_steps, void* hip_stream);
 
+/* mhdpic_step with particle sub-cycling (App. A, "Timestepping and Code
+ * Performance"): each of the n_steps steps of dt forms the cell-centred E
+ * once, from the n_CR, J_CR present at its start, and then advances the
+ * particles n_sub times by dt/n_sub with that E and the given B.  -dM and
+ * -dE_k of every sub-step accumulate; n_CR and J_CR are deposited only after
+ * the last sub-step, at the particles' final positions.  n_sub = 1 is
+ * mhdpic_step.  1 <= n_sub <= 1024, else MHDPIC_EINVAL; the move limit
+ * applies to C*|dt/n_sub|/dx.  Other arguments and waits as for mhdpic_step. */
+int mhdpic_step_sub(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps, int32_t n_sub, void* hip_stream);
+
 /* mhdpic_step through a HIP graph.  The first call (and any call whose
  * B, vg, rho, dt or n_steps differ from the cached ones) captures the n_steps
  * steps into a graph owned by the context; every call then launches that

@@ -372,17 +372,26 @@ int oracle_check_dt(const oracle_box* bx, double dt) {
     return ORACLE_OK;
 }
 
-int oracle_step(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
-                const double* rho, double dt, int n_steps, int64_t* D, int64_t* nJ_next,
-                double* E) {
+/* One MHD step of the particles: E is prepared once from the n_CR, J_CR in
+ * D[0..3] (Sec. 2.1), then every particle takes n_sub steps of dt/n_sub with
+ * that E and the caller's B (App. A, "Timestepping and Code Performance":
+ * particle sub-cycling with the fields of the half MHD step).  The corrector
+ * feedback -dM, -dE_k of every sub-step accumulates in D[4..7]; n_CR, J_CR are
+ * deposited at the particles' final positions only, as the next MHD step's
+ * predictor input, and copied into D[0..3] at the end. */
+int oracle_step_sub(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
+                    const double* rho, double dt, int n_steps, int n_sub, int64_t* D,
+                    int64_t* nJ_next, double* E) {
     int rc = check_box(bx);
     if (rc) return rc;
-    rc = oracle_check_dt(bx, dt);
+    if (n_sub < 1) return ORACLE_EINVAL;
+    double dts = dt / (double)n_sub;
+    rc = oracle_check_dt(bx, dts);
     if (rc) return rc;
     int64_t N = P->N, nc = n_cells(bx);
     double S = ldexp(1.0, bx->frac_bits);
     double C = bx->C;
-    double hdt = 0.5 * dt;
+    double hdt = 0.5 * dts;
     double hdx[3] = {0.0, 0.0, 0.0};
     for (int d = 0; d < bx->ndim; ++d) hdx[d] = hdt / bx->dx[d];
 
@@ -390,66 +399,78 @@ int oracle_step(const oracle_box* bx, oracle_particles* P, const double* B, cons
         /* Predictor: cell-centred E from the current n_CR, J_CR (Sec. 2.1). */
         oracle_fieldprep(bx, B, vg, rho, D, E);
         memset(nJ_next, 0, sizeof(int64_t) * 4 * (size_t)nc);
-        for (int64_t j = 0; j < N; ++j) {
-            int i[3];
-            double dl[3], v[3];
-            for (int d = 0; d < 3; ++d) {
-                i[d] = P->cell[d * N + j];
-                dl[d] = P->delta[d * N + j];
-                v[d] = P->v[d * N + j];
-            }
-            double m = P->m[j], qm = P->qm[j];
-
-            double g0, u0[3], ek0;
-            oracle_lorentz(v, C, &g0, u0, &ek0);
-
-            /* drift to x^(n+1/2) */
-            drift(bx, i, dl, u0, hdx);
-
-            /* TSC interpolation of E and B at x^(n+1/2) */
-            stencil sh;
-            make_stencil(bx, i, dl, &sh);
-            double Ep[3] = {0.0, 0.0, 0.0}, Bp[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < sh.nk; ++k)
+        for (int sub = 0; sub < n_sub; ++sub) {
+            const int last = sub == n_sub - 1;
+            for (int64_t j = 0; j < N; ++j) {
+                int i[3];
+                double dl[3], v[3];
                 for (int d = 0; d < 3; ++d) {
-                    Ep[d] = fma(sh.W[k], E[d * nc + sh.cell[k]], Ep[d]);
-                    Bp[d] = fma(sh.W[k], B[d * nc + sh.cell[k]], Bp[d]);
+                    i[d] = P->cell[d * N + j];
+                    dl[d] = P->delta[d * N + j];
+                    v[d] = P->v[d * N + j];
                 }
-            oracle_clean_E(Ep, Bp);
+                double m = P->m[j], qm = P->qm[j];
 
-            /* kick - rotate - kick */
-            double hq = qm * hdt;
-            double vn[3];
-            oracle_boris_kick_rotate_kick(v, Ep, Bp, hq, C, vn);
-            if (!isfinite(vn[0]) || !isfinite(vn[1]) || !isfinite(vn[2])) return ORACLE_ENONFINITE;
+                double g0, u0[3], ek0;
+                oracle_lorentz(v, C, &g0, u0, &ek0);
 
-            double g1, u1[3], ek1;
-            oracle_lorentz(vn, C, &g1, u1, &ek1);
+                /* drift to x^(n+1/2) */
+                drift(bx, i, dl, u0, hdx);
 
-            /* corrector feedback at x^(n+1/2): -dM, -dE_k */
-            for (int d = 0; d < 3; ++d) {
-                rc = deposit_amount(D + (4 + d) * nc, &sh, (-(m * (vn[d] - v[d]))) * S);
+                /* TSC interpolation of E and B at x^(n+1/2) */
+                stencil sh;
+                make_stencil(bx, i, dl, &sh);
+                double Ep[3] = {0.0, 0.0, 0.0}, Bp[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < sh.nk; ++k)
+                    for (int d = 0; d < 3; ++d) {
+                        Ep[d] = fma(sh.W[k], E[d * nc + sh.cell[k]], Ep[d]);
+                        Bp[d] = fma(sh.W[k], B[d * nc + sh.cell[k]], Bp[d]);
+                    }
+                oracle_clean_E(Ep, Bp);
+
+                /* kick - rotate - kick */
+                double hq = qm * hdt;
+                double vn[3];
+                oracle_boris_kick_rotate_kick(v, Ep, Bp, hq, C, vn);
+                if (!isfinite(vn[0]) || !isfinite(vn[1]) || !isfinite(vn[2])) return ORACLE_ENONFINITE;
+
+                double g1, u1[3], ek1;
+                oracle_lorentz(vn, C, &g1, u1, &ek1);
+
+                /* corrector feedback at x^(n+1/2): -dM, -dE_k */
+                for (int d = 0; d < 3; ++d) {
+                    rc = deposit_amount(D + (4 + d) * nc, &sh, (-(m * (vn[d] - v[d]))) * S);
+                    if (rc) return rc;
+                }
+                rc = deposit_amount(D + 7 * nc, &sh, (-(m * (ek1 - ek0))) * S);
                 if (rc) return rc;
-            }
-            rc = deposit_amount(D + 7 * nc, &sh, (-(m * (ek1 - ek0))) * S);
-            if (rc) return rc;
 
-            /* drift to x^(n+1) */
-            drift(bx, i, dl, u1, hdx);
+                /* drift to x^(n+1) */
+                drift(bx, i, dl, u1, hdx);
 
-            /* n_CR, J_CR at x^(n+1) for the next predictor */
-            rc = deposit_charge_current(bx, nJ_next, nc, i, dl, qm, m, u1, S);
-            if (rc) return rc;
+                /* n_CR, J_CR at the end of the MHD step for the next predictor */
+                if (last) {
+                    rc = deposit_charge_current(bx, nJ_next, nc, i, dl, qm, m, u1, S);
+                    if (rc) return rc;
+                }
 
-            for (int d = 0; d < 3; ++d) {
-                P->cell[d * N + j] = i[d];
-                P->delta[d * N + j] = dl[d];
-                P->v[d * N + j] = vn[d];
+                for (int d = 0; d < 3; ++d) {
+                    P->cell[d * N + j] = i[d];
+                    P->delta[d * N + j] = dl[d];
+                    P->v[d * N + j] = vn[d];
+                }
             }
         }
         memcpy(D, nJ_next, sizeof(int64_t) * 4 * (size_t)nc);
     }
     return ORACLE_OK;
+}
+
+/* n_steps steps of one particle step each (App. A.3). */
+int oracle_step(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
+                const double* rho, double dt, int n_steps, int64_t* D, int64_t* nJ_next,
+                double* E) {
+    return oracle_step_sub(bx, P, B, vg, rho, dt, n_steps, 1, D, nJ_next, E);
 }
 
 /* Global positions x = x0 + dx * ((i + 1/2) + d). */

@@ -55,6 +55,9 @@ int oracle_check_dt(const oracle_box* bx, double dt);
 int oracle_step(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
                 const double* rho, double dt, int n_steps, int64_t* D, int64_t* nJ_next,
                 double* E);
+int oracle_step_sub(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
+                    const double* rho, double dt, int n_steps, int n_sub, int64_t* D,
+                    int64_t* nJ_next, double* E);
 int oracle_positions(const oracle_box* bx, const oracle_particles* P, double* x);
 
 #endif

@@ -79,6 +79,9 @@ def lib():
         L.oracle_step.restype = ct.c_int
         L.oracle_step.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp, dp, dp,
                                   ct.c_double, ct.c_int, i64p, i64p, dp]
+        L.oracle_step_sub.restype = ct.c_int
+        L.oracle_step_sub.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp, dp, dp,
+                                      ct.c_double, ct.c_int, ct.c_int, i64p, i64p, dp]
         L.oracle_positions.restype = ct.c_int
         L.oracle_positions.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp]
         _lib = L
@@ -222,13 +225,15 @@ class System:
         if rc:
             raise OracleError(rc)
 
-    def step(self, B, vg, rho, dt: float, n_steps: int = 1):
+    def step(self, B, vg, rho, dt: float, n_steps: int = 1, n_sub: int = 1):
+        """n_steps MHD steps of dt, each of n_sub particle steps of dt/n_sub
+        with the field prepared at the MHD step's start."""
         B = np.ascontiguousarray(B, dtype=np.float64)
         vg = np.ascontiguousarray(vg, dtype=np.float64)
         rho = np.ascontiguousarray(rho, dtype=np.float64)
-        rc = lib().oracle_step(ct.byref(self._cb), ct.byref(self._P), _dp(B), _dp(vg), _dp(rho),
-                               float(dt), int(n_steps), _i64p(self.D), _i64p(self._nJ),
-                               _dp(self.E))
+        rc = lib().oracle_step_sub(ct.byref(self._cb), ct.byref(self._P), _dp(B), _dp(vg),
+                                   _dp(rho), float(dt), int(n_steps), int(n_sub),
+                                   _i64p(self.D), _i64p(self._nJ), _dp(self.E))
         if rc:
             raise OracleError(rc)
 

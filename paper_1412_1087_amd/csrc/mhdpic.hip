@@ -42,6 +42,7 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int32_t kMaxSubsteps = 1024;  // particle sub-steps per step, at most
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -388,7 +389,7 @@ int launch_initial_sort_any(mhdpic_ctx* c, hipStream_t s) {
 }
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
-int launch_push_pol(mhdpic_ctx* c, hipStream_t s) {
+int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
     constexpr int BLOCK = 256;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
@@ -405,6 +406,7 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s) {
     a.n_items = at<uint32_t>(c, L.n_items[c->it]);
     a.err = at<uint32_t>(c, L.err);
     a.NC = L.NC;
+    a.do_pred = do_pred ? 1 : 0;
     size_t lds = G::lds_bytes();
     auto kern = k_push<Pol, NDIM, TX, TY, TZ, BLOCK>;
     if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -413,25 +415,25 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s) {
 }
 
 template <int NDIM, int TX, int TY, int TZ>
-int launch_push_t(mhdpic_ctx* c, hipStream_t s) {
-    if (c->precision == MHDPIC_FP64) return launch_push_pol<F64Pol, NDIM, TX, TY, TZ>(c, s);
-    return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s);
+int launch_push_t(mhdpic_ctx* c, hipStream_t s, bool p) {
+    if (c->precision == MHDPIC_FP64) return launch_push_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, p);
+    return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, p);
 }
 
-int launch_push(mhdpic_ctx* c, hipStream_t s) {
+int launch_push(mhdpic_ctx* c, hipStream_t s, bool p) {
     const TileShape& t = c->tile;
     if (c->ndim == 2) {
-        if (t.x == 16 && t.y == 16) return launch_push_t<2, 16, 16, 1>(c, s);
-        if (t.x == 32 && t.y == 16) return launch_push_t<2, 32, 16, 1>(c, s);
-        if (t.x == 8 && t.y == 8) return launch_push_t<2, 8, 8, 1>(c, s);
-        if (t.x == 32 && t.y == 32) return launch_push_t<2, 32, 32, 1>(c, s);
-        if (t.x == 64 && t.y == 16) return launch_push_t<2, 64, 16, 1>(c, s);
+        if (t.x == 16 && t.y == 16) return launch_push_t<2, 16, 16, 1>(c, s, p);
+        if (t.x == 32 && t.y == 16) return launch_push_t<2, 32, 16, 1>(c, s, p);
+        if (t.x == 8 && t.y == 8) return launch_push_t<2, 8, 8, 1>(c, s, p);
+        if (t.x == 32 && t.y == 32) return launch_push_t<2, 32, 32, 1>(c, s, p);
+        if (t.x == 64 && t.y == 16) return launch_push_t<2, 64, 16, 1>(c, s, p);
     } else {
-        if (t.x == 8 && t.y == 4 && t.z == 4) return launch_push_t<3, 8, 4, 4>(c, s);
-        if (t.x == 8 && t.y == 8 && t.z == 4) return launch_push_t<3, 8, 8, 4>(c, s);
-        if (t.x == 4 && t.y == 4 && t.z == 4) return launch_push_t<3, 4, 4, 4>(c, s);
-        if (t.x == 8 && t.y == 8 && t.z == 8) return launch_push_t<3, 8, 8, 8>(c, s);
-        if (t.x == 16 && t.y == 4 && t.z == 4) return launch_push_t<3, 16, 4, 4>(c, s);
+        if (t.x == 8 && t.y == 4 && t.z == 4) return launch_push_t<3, 8, 4, 4>(c, s, p);
+        if (t.x == 8 && t.y == 8 && t.z == 4) return launch_push_t<3, 8, 8, 4>(c, s, p);
+        if (t.x == 4 && t.y == 4 && t.z == 4) return launch_push_t<3, 4, 4, 4>(c, s, p);
+        if (t.x == 8 && t.y == 8 && t.z == 8) return launch_push_t<3, 8, 8, 8>(c, s, p);
+        if (t.x == 16 && t.y == 4 && t.z == 4) return launch_push_t<3, 16, 4, 4>(c, s, p);
     }
     return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");
 }
@@ -509,9 +511,10 @@ int post_error_copy(mhdpic_ctx* c, hipStream_t s) {
 }
 
 int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
-                    const double* dt, int32_t n_steps) {
+                    const double* dt, int32_t n_steps, int32_t n_sub) {
     if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
     if (!dt || n_steps < 0) return fail(MHDPIC_EINVAL, "dt is NULL or n_steps < 0");
+    if (n_sub < 1 || n_sub > kMaxSubsteps) return fail(MHDPIC_EINVAL, "n_sub out of range");
     if (c->L.NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
     bool any_hall = false;
     for (auto& b : c->boxes) any_hall |= b.hall != 0;
@@ -520,7 +523,7 @@ int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const doub
         const mhdpic_box& bx = c->boxes[b];
         if (!std::isfinite(dt[b])) return fail(MHDPIC_EINVAL, "dt must be finite");
         for (int d = 0; d < c->ndim; ++d) {
-            double cells = bx.C * std::fabs(dt[b]) / bx.dx[d];
+            double cells = bx.C * std::fabs(dt[b] / (double)n_sub) / bx.dx[d];
             if (!(cells <= bx.max_move_cells * (1.0 - 1e-12)))
                 return fail(MHDPIC_ERANGE, "C*|dt|/dx exceeds max_move_cells");
         }
@@ -531,16 +534,17 @@ int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const doub
 // Refreshes the per-call step constants on the device when dt changed.  A
 // stream being captured cannot take the upload (it would be replayed from
 // host memory): dt must then already be current.
-int set_dt(mhdpic_ctx* c, const double* dt, hipStream_t s, bool capturing) {
+int set_dt(mhdpic_ctx* c, const double* dt, int32_t n_sub, hipStream_t s, bool capturing) {
     bool changed = !c->dt_uploaded;
-    for (int b = 0; b < c->nb && !changed; ++b) changed = c->bdev[b].dt != dt[b];
+    for (int b = 0; b < c->nb && !changed; ++b) changed = c->bdev[b].dt != dt[b] / (double)n_sub;
     if (!changed) return MHDPIC_OK;
     if (capturing)
         return fail(MHDPIC_EINVAL, "dt differs from the last call: step once before capturing");
     for (int b = 0; b < c->nb; ++b) {
         BoxDev& d = c->bdev[b];
-        d.dt = dt[b];
-        d.hdt = 0.5 * dt[b];
+        const double dts = dt[b] / (double)n_sub;  // the particle step
+        d.dt = dts;
+        d.hdt = 0.5 * dts;
         for (int k = 0; k < 3; ++k) d.hdx[k] = k < c->ndim ? d.hdt / c->boxes[b].dx[k] : 0.0;
     }
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
@@ -550,10 +554,12 @@ int set_dt(mhdpic_ctx* c, const double* dt, hipStream_t s, bool capturing) {
     return MHDPIC_OK;
 }
 
-// The kernels of n_steps steps: re-binning for this call's dt, then per step
-// field preparation, the push and (except after the last) re-binning.
+// The kernels of n_steps steps of n_sub particle sub-steps each: re-binning
+// for this call's dt, then per step field preparation and per sub-step the
+// push (n_CR, J_CR at the last sub-step only) and, except after the call's
+// last push, re-binning.
 int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
-                  int32_t n_steps, hipStream_t s, bool allow_timing) {
+                  int32_t n_steps, int32_t n_sub, hipStream_t s, bool allow_timing) {
     if (!rho) rho = B;  // never read without the Hall term
     const bool saved = c->timing;
     c->timing = c->timing && allow_timing;
@@ -573,16 +579,20 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
             int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
             fill_i64(next, 4 * c->L.NC, s);
         }
-        {
-            PhaseTimer t(c, s, 2);
-            rc = launch_push(c, s);
+        for (int sub = 0; sub < n_sub && !rc; ++sub) {
+            const bool last_sub = sub + 1 == n_sub;
+            {
+                PhaseTimer t(c, s, 2);
+                rc = launch_push(c, s, last_sub);
+            }
+            if (rc) break;
+            if (st + 1 < n_steps || !last_sub) {
+                PhaseTimer t(c, s, 0);
+                rc = launch_bin_any(c, s, false);
+            }
         }
         if (rc) break;
         c->nj = 1 - c->nj;
-        if (st + 1 < n_steps) {
-            PhaseTimer t(c, s, 0);
-            rc = launch_bin_any(c, s, false);
-        }
     }
     c->timing = saved;
     if (rc) return rc;
@@ -770,7 +780,12 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
 
 int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
                 const double* dt, int32_t n_steps, void* hip_stream) {
-    int rc = check_step_args(c, B, vg, rho, dt, n_steps);
+    return mhdpic_step_sub(c, B, vg, rho, dt, n_steps, 1, hip_stream);
+}
+
+int mhdpic_step_sub(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps, int32_t n_sub, void* hip_stream) {
+    int rc = check_step_args(c, B, vg, rho, dt, n_steps, n_sub);
     if (rc) return rc;
     rc = poll_error(c);
     if (rc) return rc;
@@ -780,9 +795,9 @@ int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* 
     HIP_TRY(hipStreamIsCapturing(s, &cap));
     const bool capturing = cap != hipStreamCaptureStatusNone;
     c->last_stream = s;
-    rc = set_dt(c, dt, s, capturing);
+    rc = set_dt(c, dt, n_sub, s, capturing);
     if (rc) return rc;
-    rc = enqueue_steps(c, B, vg, rho, n_steps, s, !capturing);
+    rc = enqueue_steps(c, B, vg, rho, n_steps, n_sub, s, !capturing);
     if (rc) return rc;
     if (capturing) return MHDPIC_OK;
     return post_error_copy(c, s);
@@ -790,7 +805,7 @@ int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* 
 
 int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
                       const double* dt, int32_t n_steps, void* hip_stream) {
-    int rc = check_step_args(c, B, vg, rho, dt, n_steps);
+    int rc = check_step_args(c, B, vg, rho, dt, n_steps, 1);
     if (rc) return rc;
     if (n_steps <= 0 || n_steps % 2) return fail(MHDPIC_EINVAL, "n_steps must be even and > 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -804,10 +819,10 @@ int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const do
             HIP_TRY(hipGraphExecDestroy(c->graph_exec));
             c->graph_exec = nullptr;
         }
-        rc = set_dt(c, dt, s, false);  // uploads happen outside the graph
+        rc = set_dt(c, dt, 1, s, false);  // uploads happen outside the graph
         if (rc) return rc;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_steps(c, B, vg, rho, n_steps, s, false);
+        rc = enqueue_steps(c, B, vg, rho, n_steps, 1, s, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (rc) {

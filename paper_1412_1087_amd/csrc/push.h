@@ -33,6 +33,7 @@ struct PushArgsT {
     const uint32_t* n_items;
     uint32_t* err;
     int64_t NC;
+    int32_t do_pred;             // 0: skip n_CR, J_CR (a sub-step before the last)
 };
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
@@ -135,7 +136,9 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) Dc[q * G::NFF + c] = 0ull;
     }
-    for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
+    const bool do_pred = a.do_pred != 0;
+    if (do_pred)
+        for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
     __syncthreads();
 
     const double C = bx.C, C2 = bx.C2, iC = bx.iC, S = bx.S, hdt = bx.hdt;
@@ -222,20 +225,23 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         if (NDIM == 3) i[2] = wrap_shift(i[2], t2, bx.n[2]);
         const int pbase = corner + (NDIM == 3 ? (t2 * G::PY + t1) * G::PX + t0 : t1 * G::PX + t0);
 
-        // n_CR, J_CR at x^(n+1): the predictor input of the next step
-        Pol::weights(dl[0], wx);
-        Pol::weights(dl[1], wy);
-        if (NDIM == 3) Pol::weights(dl[2], wz);
-        const double qmm = qm * m;
-        double Vp[4];
-        Vp[0] = qmm * S;
-        Vp[1] = (qmm * (double)k1.u[0]) * S;
-        Vp[2] = (qmm * (double)k1.u[1]) * S;
-        Vp[3] = (qmm * (double)k1.u[2]) * S;
-        bool okp = fabs(Vp[0]) < kMaxAmount && fabs(Vp[1]) < kMaxAmount &&
-                   fabs(Vp[2]) < kMaxAmount && fabs(Vp[3]) < kMaxAmount;
-        if (okp) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
-        else errbits |= ERRBIT_RANGE;
+        // n_CR, J_CR at x^(n+1): the predictor input of the next step (at
+        // the last sub-step of a sub-cycled step only)
+        if (do_pred) {
+            Pol::weights(dl[0], wx);
+            Pol::weights(dl[1], wy);
+            if (NDIM == 3) Pol::weights(dl[2], wz);
+            const double qmm = qm * m;
+            double Vp[4];
+            Vp[0] = qmm * S;
+            Vp[1] = (qmm * (double)k1.u[0]) * S;
+            Vp[2] = (qmm * (double)k1.u[1]) * S;
+            Vp[3] = (qmm * (double)k1.u[2]) * S;
+            bool okp = fabs(Vp[0]) < kMaxAmount && fabs(Vp[1]) < kMaxAmount &&
+                       fabs(Vp[2]) < kMaxAmount && fabs(Vp[3]) < kMaxAmount;
+            if (okp) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
+            else errbits |= ERRBIT_RANGE;
+        }
 
         // store x^(n+1), v^(n+1)
         a.P.cell[j] = pack_cell<NDIM>(i[0], i[1], i[2]);
@@ -278,7 +284,7 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
             if (val) atomicAdd((unsigned long long*)&a.Dcorr[q * NC + g], val);
         }
     }
-    for (int c = threadIdx.x; c < G::NP; c += BLOCK) {
+    for (int c = threadIdx.x; c < (do_pred ? G::NP : 0); c += BLOCK) {
         int lx, ly, lz;
         G::coords(c, lx, ly, lz);
         bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);

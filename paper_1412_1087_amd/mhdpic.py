@@ -24,7 +24,7 @@ EXPORTED = [
     "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
-    "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune",
+    "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
 ]
 
 
@@ -60,6 +60,9 @@ def lib():
                                   ct.c_int32, vp, vp, vp, vp, vp, sz, vp, ct.POINTER(vp)]
         L.mhdpic_step.restype = ct.c_int
         L.mhdpic_step.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32, vp]
+        L.mhdpic_step_sub.restype = ct.c_int
+        L.mhdpic_step_sub.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32,
+                                      ct.c_int32, vp]
         L.mhdpic_deposit_read.restype = ct.c_int
         L.mhdpic_deposit_read.argtypes = [vp, vp, ct.c_int32, vp]
         L.mhdpic_particles_read.restype = ct.c_int
@@ -186,12 +189,18 @@ class Context:
         self.device = dev
 
     def step(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor | None, dt, n_steps: int = 1,
-             stream=None):
+             stream=None, n_sub: int = 1):
+        """n_steps steps of dt; with n_sub > 1 each takes n_sub particle
+        sub-steps of dt/n_sub through the field formed at its start."""
         if isinstance(dt, (int, float)):
             dt = [float(dt)] * len(self.boxes)
         dts = (ct.c_double * len(self.boxes))(*[float(a) for a in dt])
-        _check(lib().mhdpic_step(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
-                                 _stream(stream)))
+        if n_sub == 1:
+            _check(lib().mhdpic_step(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                     _stream(stream)))
+        else:
+            _check(lib().mhdpic_step_sub(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                         int(n_sub), _stream(stream)))
 
     def step_graph(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor | None, dt,
                    n_steps: int, stream):

@@ -49,11 +49,11 @@ class GpuRun:
         self.part_off = np.cumsum([0] + [w.N for w in self.wls])
         torch.cuda.synchronize()
 
-    def step(self, n_steps=1, dts=None):
+    def step(self, n_steps=1, dts=None, n_sub=1):
         import torch
         if dts is None:
             dts = [w.dt for w in self.wls]
-        self.ctx.step(self.B, self.vg, self.rho, dts, n_steps)
+        self.ctx.step(self.B, self.vg, self.rho, dts, n_steps, n_sub=n_sub)
         torch.cuda.synchronize()
 
     def deposits(self):

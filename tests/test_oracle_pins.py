@@ -538,3 +538,67 @@ def test_move_limit_is_enforced():
     assert O.check_dt(box, 0.1001) == O.ERANGE
     box1 = O.Box(ndim=2, n=(8, 8, 1), C=20.0, max_move_cells=1)
     assert O.check_dt(box1, 0.0501) == O.ERANGE
+
+
+# --------------------------------------------------------------------------
+# particle sub-cycling (App. A, "Timestepping and Code Performance")
+# --------------------------------------------------------------------------
+
+def _sub_workload(ndim, hall, seed):
+    from paper_1412_1087_amd import workloads as W
+    if ndim == 2:
+        wl = W.gyro2d(nx=8, ny=6, ppc=4, seed=seed)
+    else:
+        wl = W.bell3d(n=(6, 5, 4), ppc=3, seed=seed, hall=hall)
+    box = O.Box(ndim=ndim, n=wl.box.n, C=wl.box.C, hall=hall)
+    return wl, box
+
+
+@pytest.mark.parametrize("ndim,n_sub", [(2, 2), (2, 5), (3, 3)])
+def test_subcycling_without_hall_equals_plain_substeps(ndim, n_sub):
+    """Without the Hall term E does not depend on n_CR, J_CR, so MHD steps of
+    n_sub particle sub-steps equal plain steps of dt/n_sub bit for bit: the
+    same states, the same accumulated -dM, -dE_k and the same final n_CR,
+    J_CR (deposited once, at the end of each MHD step)."""
+    wl, box = _sub_workload(ndim, 0, 31 + n_sub)
+    a = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    b = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    a.step(wl.B, wl.vg, wl.rho, wl.dt, n_steps=2, n_sub=n_sub)
+    for _ in range(2 * n_sub):
+        b.step(wl.B, wl.vg, wl.rho, wl.dt / n_sub, 1)
+    assert (a.D == b.D).all()
+    assert (a.v == b.v).all()
+    assert (a.positions() == b.positions()).all()
+
+
+@pytest.mark.parametrize("n_sub", [2, 4])
+def test_subcycling_with_hall_holds_the_field_of_the_step_start(n_sub):
+    """With the Hall term every sub-step uses the E prepared from the n_CR,
+    J_CR present at the start of the MHD step: plain steps of dt/n_sub with
+    those n_CR, J_CR put back before each one give the same result bit for
+    bit, while letting them update between sub-steps does not."""
+    wl, box = _sub_workload(3, 1, 41 + n_sub)
+    a = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    b = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    c = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    a.step(wl.B, wl.vg, wl.rho, wl.dt, 1, n_sub=n_sub)
+    nJ0 = b.D[:4].copy()
+    for _ in range(n_sub):
+        b.D[:4] = nJ0
+        b.step(wl.B, wl.vg, wl.rho, wl.dt / n_sub, 1)
+        c.step(wl.B, wl.vg, wl.rho, wl.dt / n_sub, 1)
+    assert (a.D == b.D).all()
+    assert (a.v == b.v).all()
+    assert (a.positions() == b.positions()).all()
+    assert not (a.v == c.v).all()
+
+
+def test_subcycling_rejects_zero_substeps_and_checks_the_substep_move():
+    wl, box = _sub_workload(2, 0, 51)
+    s = O.System(box, wl.x, wl.v, wl.m, wl.qm)
+    with pytest.raises(O.OracleError):
+        s.step(wl.B, wl.vg, wl.rho, wl.dt, 1, n_sub=0)
+    # a dt beyond the move limit for one step is fine once split in three
+    big = 2.5 * 0.98 * box.max_move_cells * 1.0 / box.C
+    assert O.check_dt(box, big) == O.ERANGE
+    s.step(wl.B, wl.vg, wl.rho, big, 1, n_sub=3)
