@@ -219,6 +219,31 @@ def run_strip_form(steps: int, warmup: int):
     return out
 
 
+FEEDBACK_BYTES_PER_CELL = 168  # read n_CR, J_CR (32), B, v_g (48), rho (8); write 10 doubles
+
+
+def time_feedback(ctx, B, vg, rho, n_cells: int, reps: int = 20):
+    """Average launch time of the cell-centred feedback kernel and its share
+    of the HBM peak at 168 algorithmic bytes per cell."""
+    import torch
+    out = torch.empty((10, n_cells), dtype=torch.float64, device=B.device)
+    ctx.feedback(B, vg, rho, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.feedback(B, vg, rho, out)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    gbs = FEEDBACK_BYTES_PER_CELL * n_cells / (us * 1e-6) / 1e9
+    log(f"feedback: {n_cells} cells, {us:.1f} us per launch, {gbs:.0f} GB/s")
+    return {"cells": n_cells, "avg_launch_us": round(us, 2),
+            "bytes_per_cell": FEEDBACK_BYTES_PER_CELL, "achieved_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def run_precision_form(steps: int, warmup: int):
     """Precision form on the 128^3, 32-per-cell beam box, against the binary64
     path on the same seed: throughput of both and the one-step error."""
@@ -257,6 +282,7 @@ def run_precision_form(steps: int, warmup: int):
     out["one_step_error_vs_fp64"] = err
     del x64, v64, x32, v32, D64, D32
     ms64 = _time_steps(ctx64, B, vg, rho, wl.dt, steps, warmup)
+    out["feedback"] = time_feedback(ctx64, B, vg, rho, box.n_cells)
     ctx64.destroy()
     del ctx64
     torch.cuda.empty_cache()
@@ -325,7 +351,7 @@ def run_batched_form(steps: int):
 # CPU baseline: the oracle on a bounded sample
 # --------------------------------------------------------------------------
 
-def run_cpu_baseline(wl, label: str, sample_div: int = 16, steps: int = 3):
+def run_cpu_baseline(wl, label: str, sample_div: int = 8, steps: int = 6):
     from oracle import oracle as O
     O.build(force=not os.path.exists(O.LIB))
     ns = max(1, wl.N // sample_div)

@@ -132,7 +132,26 @@ int mhdpic_step(mhdpic_ctx* ctx, const double* B, const double* vg, const double
 int mhdpic_step_sub(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
                     const double* dt, int32_t n_steps, int32_t n_sub, void* hip_stream);
 
-/* mhdpic_step through a HIP graph.  The first call (and any call whose
+/* Cell-centred CR feedback of the predictor step (App. A.3: computed at cell
+ * centres from the n_CR, J_CR deposited at the particles' current positions,
+ * R from the gas density, E0 = -v_g x B and B).  Code units: c = 1 and no
+ * factors of 4 pi (as in App. B); n_CR = D0 2^-frac_bits / dV, J_CR likewise.
+ *   B, vg  device, [3][cells] doubles; rho device, [cells] doubles, > 0
+ *   out    device, [10][cells] doubles, written:
+ *     0-2  -F_CR, F_CR = (1-R)(n_CR E0 + J_CR x B)   (Sec. 2.2 eq. lorentz2): the
+ *          momentum source of the gas (eq. gasmotion)
+ *     3    -(1-R) J_CR . E0 = -v_g . F_CR (eqs. engeq, eng): its energy source
+ *     4-6  (E - E0) x B with E = E0 - F_CR/n_g (eq. emfcr2): the CR-Hall part
+ *          of the energy flux (eq. engeq; times c/4pi in Gaussian units)
+ *     7-9  Lambda = R (u_CR - v_g) / v_A, u_CR = J_CR/n_CR, v_A = |B|/sqrt(rho)
+ *          (eq. lambda); 0 where n_CR = 0 or B = 0
+ * R = n_CR/(n_g + n_CR), n_g = qomc_gas rho.  In a box with hall = 0, R is
+ * taken as 0 in channels 0-6 (the particles feel E0), so 4-6 are 0; Lambda
+ * keeps the physical R.  Enqueued on the stream; does not wait. */
+int mhdpic_feedback(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
+                    double* out, void* hip_stream);
+
+/* mhdpic_step through a HIP graph./* mhdpic_step through a HIP graph.  The first call (and any call whose
  * B, vg, rho, dt or n_steps differ from the cached ones) captures the n_steps
  * steps into a graph owned by the context; every call then launches that
  * graph, so one launch advances all boxes n_steps steps.  n_steps must be even

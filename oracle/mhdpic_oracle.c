@@ -291,6 +291,61 @@ int oracle_fieldprep(const oracle_box* bx, const double* B, const double* vg, co
     return ORACLE_OK;
 }
 
+/* Cell-centred feedback of the predictor step (App. A.3: computed at cell
+ * centres from n_CR, J_CR deposited at the particles' positions, R from the gas
+ * density, E0 and B).  Per cell, in code units (c = 1, no 4 pi):
+ *   out[0..2]  -F_CR, F_CR = (1-R)(n_CR E0 + J_CR x B)       (Sec. 2.2, eq. lorentz2)
+ *   out[3]     -(1-R) J_CR . E0                               (eq. engeq, first equality)
+ *   out[4..6]  (E - E0) x B, E the field of eq. emfcr2       (eq. engeq, energy flux)
+ *   out[7..9]  Lambda = R (u_CR - v_g) / v_A, u_CR = J_CR/n_CR,
+ *              v_A = |B|/sqrt(rho); zero where n_CR = 0 or B = 0   (eq. lambda)
+ * Without the Hall term R is taken as 0 in out[0..6] (the particles then feel
+ * E = E0); Lambda always uses R = n_CR/(n_g + n_CR). */
+int oracle_feedback(const oracle_box* bx, const double* B, const double* vg, const double* rho,
+                    const int64_t* D, double* out) {
+    int64_t nc = n_cells(bx);
+    double iS = ldexp(1.0, -bx->frac_bits);
+    double dV = bx->dx[0] * bx->dx[1];
+    if (bx->ndim == 3) dV = dV * bx->dx[2];
+    for (int64_t c = 0; c < nc; ++c) {
+        double b[3] = {B[c], B[nc + c], B[2 * nc + c]};
+        double g[3] = {vg[c], vg[nc + c], vg[2 * nc + c]};
+        double e0[3];
+        e0[0] = -(g[1] * b[2] - g[2] * b[1]);
+        e0[1] = -(g[2] * b[0] - g[0] * b[2]);
+        e0[2] = -(g[0] * b[1] - g[1] * b[0]);
+        double n = ((double)D[c] * iS) / dV;
+        double J[3];
+        for (int d = 0; d < 3; ++d) J[d] = ((double)D[(1 + d) * nc + c] * iS) / dV;
+        double ng = bx->qomc_gas * rho[c];
+        double RL = n / (ng + n);
+        double R = bx->hall ? RL : 0.0;
+        double jxb[3];
+        jxb[0] = J[1] * b[2] - J[2] * b[1];
+        jxb[1] = J[2] * b[0] - J[0] * b[2];
+        jxb[2] = J[0] * b[1] - J[1] * b[0];
+        double e[3];
+        for (int d = 0; d < 3; ++d) {
+            double F = (1.0 - R) * (n * e0[d] + jxb[d]);
+            out[d * nc + c] = -F;
+            e[d] = bx->hall ? e0[d] - F / ng : e0[d];
+        }
+        double je0 = (J[0] * e0[0] + J[1] * e0[1]) + J[2] * e0[2];
+        out[3 * nc + c] = -((1.0 - R) * je0);
+        double de[3] = {e[0] - e0[0], e[1] - e0[1], e[2] - e0[2]};
+        out[4 * nc + c] = de[1] * b[2] - de[2] * b[1];
+        out[5 * nc + c] = de[2] * b[0] - de[0] * b[2];
+        out[6 * nc + c] = de[0] * b[1] - de[1] * b[0];
+        double bb = (b[0] * b[0] + b[1] * b[1]) + b[2] * b[2];
+        for (int d = 0; d < 3; ++d) out[(7 + d) * nc + c] = 0.0;
+        if (n != 0.0 && bb > 0.0) {
+            double vA = sqrt(bb / rho[c]);
+            for (int d = 0; d < 3; ++d) out[(7 + d) * nc + c] = (RL * (J[d] / n - g[d])) / vA;
+        }
+    }
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Initialisation                                                           */
 /* ------------------------------------------------------------------------ */

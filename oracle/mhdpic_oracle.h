@@ -49,6 +49,8 @@ void oracle_boris_kick_rotate_kick(const double v[3], const double E[3], const d
 void oracle_tsc_weights(double d, double w[3]);
 int oracle_fieldprep(const oracle_box* bx, const double* B, const double* vg, const double* rho,
                      const int64_t* D, double* E);
+int oracle_feedback(const oracle_box* bx, const double* B, const double* vg, const double* rho,
+                    const int64_t* D, double* out);
 int oracle_init(const oracle_box* bx, oracle_particles* P, const double* x, const double* v,
                 const double* m, const double* qm, int64_t* D);
 int oracle_check_dt(const oracle_box* bx, double dt);

@@ -82,6 +82,8 @@ def lib():
         L.oracle_step_sub.restype = ct.c_int
         L.oracle_step_sub.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp, dp, dp,
                                       ct.c_double, ct.c_int, ct.c_int, i64p, i64p, dp]
+        L.oracle_feedback.restype = ct.c_int
+        L.oracle_feedback.argtypes = [ct.POINTER(OracleBox), dp, dp, dp, i64p, dp]
         L.oracle_positions.restype = ct.c_int
         L.oracle_positions.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp]
         _lib = L
@@ -248,6 +250,11 @@ class System:
             raise OracleError(rc)
         return E
 
+    def feedback(self, B, vg, rho):
+        """The 10 cell-centred predictor feedback channels from the current
+        n_CR, J_CR (see the function feedback)."""
+        return feedback(self.box, B, vg, rho, self.D)
+
     def positions(self):
         x = np.zeros((3, self.N))
         lib().oracle_positions(ct.byref(self._cb), ct.byref(self._P), _dp(x))
@@ -268,6 +275,20 @@ def fieldprep(box: Box, B, vg, rho, D):
     if rc:
         raise OracleError(rc)
     return E
+
+
+def feedback(box: Box, B, vg, rho, D):
+    """[10][cells]: -F_CR, -(1-R) J_CR.E0, (E-E0)xB, Lambda (App. A.3 predictor)."""
+    cb = box.c_struct()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    vg = np.ascontiguousarray(vg, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.int64)
+    out = np.zeros((10, box.n_cells))
+    rc = lib().oracle_feedback(ct.byref(cb), _dp(B), _dp(vg), _dp(rho), _i64p(D), _dp(out))
+    if rc:
+        raise OracleError(rc)
+    return out
 
 
 def check_dt(box: Box, dt: float) -> int:

@@ -358,6 +358,67 @@ __global__ void k_fieldprep(TF* __restrict__ EB, const double* __restrict__ B,
     o[5] = (TF)b2;
 }
 
+// Cell-centred feedback of the predictor step (App. A.3), in code units
+// (c = 1, no 4 pi), from n_CR, J_CR at the particles' current positions:
+//   out[0..2] -F_CR = -(1-R)(n_CR E0 + J_CR x B)      (eq. lorentz2, gasmotion)
+//   out[3]    -(1-R) J_CR . E0                         (eq. engeq)
+//   out[4..6] (E - E0) x B                             (eq. engeq, energy flux)
+//   out[7..9] R (u_CR - v_g) / v_A, v_A = |B|/sqrt(rho), 0 where n_CR = 0 or
+//             B = 0                                    (eq. lambda)
+// Without the Hall term R is 0 in out[0..6]; Lambda keeps n_CR/(n_g + n_CR).
+// The operations are those of the field preparation, in the same order.
+__global__ void k_feedback(double* __restrict__ out, const double* __restrict__ B,
+                           const double* __restrict__ vg, const double* __restrict__ rho,
+                           const int64_t* __restrict__ nJ, const BoxDev* __restrict__ boxes,
+                           const int64_t* __restrict__ cell_off, int nb, int64_t NC) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= NC) return;
+    const BoxDev& bx = boxes[find_box(cell_off, nb, c)];
+    const double b0 = B[c], b1 = B[NC + c], b2 = B[2 * NC + c];
+    const double g0 = vg[c], g1 = vg[NC + c], g2 = vg[2 * NC + c];
+    double e0[3];
+    e0[0] = -(g1 * b2 - g2 * b1);
+    e0[1] = -(g2 * b0 - g0 * b2);
+    e0[2] = -(g0 * b1 - g1 * b0);
+    const double n = ((double)nJ[c] * bx.iS) / bx.dV;
+    double J[3];
+    J[0] = ((double)nJ[NC + c] * bx.iS) / bx.dV;
+    J[1] = ((double)nJ[2 * NC + c] * bx.iS) / bx.dV;
+    J[2] = ((double)nJ[3 * NC + c] * bx.iS) / bx.dV;
+    const double r = rho[c];
+    const double ng = bx.qg * r;
+    const double RL = n / (ng + n);
+    const double R = bx.hall ? RL : 0.0;
+    double jxb[3];
+    jxb[0] = J[1] * b2 - J[2] * b1;
+    jxb[1] = J[2] * b0 - J[0] * b2;
+    jxb[2] = J[0] * b1 - J[1] * b0;
+    double de[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double F = (1.0 - R) * (n * e0[d] + jxb[d]);
+        out[d * NC + c] = -F;
+        const double e = bx.hall ? e0[d] - F / ng : e0[d];
+        de[d] = e - e0[d];
+    }
+    const double je0 = (J[0] * e0[0] + J[1] * e0[1]) + J[2] * e0[2];
+    out[3 * NC + c] = -((1.0 - R) * je0);
+    out[4 * NC + c] = de[1] * b2 - de[2] * b1;
+    out[5 * NC + c] = de[2] * b0 - de[0] * b2;
+    out[6 * NC + c] = de[0] * b1 - de[1] * b0;
+    const double bb = (b0 * b0 + b1 * b1) + b2 * b2;
+    double lam[3] = {0.0, 0.0, 0.0};
+    if (n != 0.0 && bb > 0.0) {
+        const double vA = sqrt(bb / r);
+        lam[0] = (RL * (J[0] / n - g0)) / vA;
+        lam[1] = (RL * (J[1] / n - g1)) / vA;
+        lam[2] = (RL * (J[2] / n - g2)) / vA;
+    }
+    out[7 * NC + c] = lam[0];
+    out[8 * NC + c] = lam[1];
+    out[9 * NC + c] = lam[2];
+}
+
 // ---------------------------------------------------------------------------
 // read-out in the original particle order
 // ---------------------------------------------------------------------------

@@ -940,6 +940,21 @@ int mhdpic_deposit_read(mhdpic_ctx* c, int64_t* out, int32_t reset_accumulated, 
     return MHDPIC_OK;
 }
 
+int mhdpic_feedback(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                    double* out, void* hip_stream) {
+    if (!c || !out) return fail(MHDPIC_EINVAL, "ctx or out is NULL");
+    const Layout& L = c->L;
+    if (L.NC > 0 && (!B || !vg || !rho)) return fail(MHDPIC_EINVAL, "B, vg or rho is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    if (L.NC == 0) return MHDPIC_OK;
+    const int64_t* nJcur = at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1);
+    hipLaunchKernelGGL(k_feedback, dim3(grid_for(L.NC, 256)), dim3(256), 0, s, out, B, vg, rho,
+                       nJcur, at<BoxDev>(c, L.boxes), at<int64_t>(c, L.cell_off), c->nb, L.NC);
+    HIP_TRY(hipGetLastError());
+    return MHDPIC_OK;
+}
+
 int mhdpic_particles_read(mhdpic_ctx* c, double* x, double* v, void* hip_stream) {
     if (!c || !x || !v) return fail(MHDPIC_EINVAL, "ctx, x or v is NULL");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -25,6 +25,7 @@ EXPORTED = [
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
+    "mhdpic_feedback",
 ]
 
 
@@ -63,6 +64,8 @@ def lib():
         L.mhdpic_step_sub.restype = ct.c_int
         L.mhdpic_step_sub.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32,
                                       ct.c_int32, vp]
+        L.mhdpic_feedback.restype = ct.c_int
+        L.mhdpic_feedback.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mhdpic_deposit_read.restype = ct.c_int
         L.mhdpic_deposit_read.argtypes = [vp, vp, ct.c_int32, vp]
         L.mhdpic_particles_read.restype = ct.c_int
@@ -210,6 +213,16 @@ class Context:
         dts = (ct.c_double * len(self.boxes))(*[float(a) for a in dt])
         _check(lib().mhdpic_step_graph(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
                                        _stream(stream)))
+
+    def feedback(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """[10][cells] doubles: -F_CR, -(1-R) J_CR.E0, (E-E0)xB, Lambda from the
+        current n_CR, J_CR (the predictor step's cell-centred feedback)."""
+        if out is None:
+            out = torch.empty((10, self.n_cells), dtype=torch.float64, device=self.device)
+        _check(lib().mhdpic_feedback(self._h, _ptr(B), _ptr(vg), _ptr(rho), _ptr(out),
+                                     _stream(stream)))
+        return out
 
     def deposit_read(self, reset_accumulated: bool = False, out: torch.Tensor | None = None,
                      stream=None) -> torch.Tensor:

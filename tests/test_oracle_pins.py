@@ -602,3 +602,96 @@ def test_subcycling_rejects_zero_substeps_and_checks_the_substep_move():
     big = 2.5 * 0.98 * box.max_move_cells * 1.0 / box.C
     assert O.check_dt(box, big) == O.ERANGE
     s.step(wl.B, wl.vg, wl.rho, big, 1, n_sub=3)
+
+
+# --------------------------------------------------------------------------
+# cell-centred predictor feedback (App. A.3; Sec. 2.2 eqs. lorentz2, gasmotion,
+# engeq, eng; eq. lambda)
+# --------------------------------------------------------------------------
+
+def _feedback_cells(hall, seed):
+    rng = np.random.default_rng(seed)
+    box = O.Box(ndim=3, n=(5, 4, 3), hall=hall, qomc_gas=1.3, frac_bits=40)
+    nc = box.n_cells
+    B, vg, rho = _random_cells(nc, rng)
+    D = np.zeros((8, nc), dtype=np.int64)
+    n = 0.05 * 1.3 * rho * rng.uniform(0.5, 1.5, size=nc)
+    ucr = rng.normal(size=(3, nc)) * 10.0
+    D[0] = np.round(n * 2.0 ** 40).astype(np.int64)
+    D[1:4] = np.round(n * ucr * 2.0 ** 40).astype(np.int64)
+    D[:, 7] = 0                      # one cell without CRs
+    return box, B, vg, rho, D
+
+
+def test_feedback_hall_identities():
+    """-F_CR is the opposite of the Lorentz force n_CR E + J_CR x B felt in the
+    Hall field (eq. lorentz with the field of eq. emfcr2 from field-prep);
+    v_g . F_CR = J_CR . E = (1-R) J_CR . E0 (eq. eng); F_CR is normal to B;
+    the flux term is (E - E0) x B with the same E."""
+    box, B, vg, rho, D = _feedback_cells(1, 61)
+    out = O.feedback(box, B, vg, rho, D)
+    E = O.fieldprep(box, B, vg, rho, D)
+    E0 = -np.cross(vg.T, B.T).T
+    n = D[0] / 2.0 ** 40
+    J = D[1:4] / 2.0 ** 40
+    F = -out[0:3]
+    lor = n * E + np.cross(J.T, B.T).T
+    mag = np.abs(n) * np.linalg.norm(E, axis=0) + np.linalg.norm(J, axis=0) * np.linalg.norm(B, axis=0)
+    assert (np.linalg.norm(F - lor, axis=0) <= 1e-12 * mag).all()
+    assert (np.abs((F * B).sum(axis=0)) <= 1e-12 * mag * np.linalg.norm(B, axis=0)).all()
+    w = -out[3]
+    magw = np.linalg.norm(J, axis=0) * np.linalg.norm(E0, axis=0)
+    assert (np.abs((vg * F).sum(axis=0) - w) <= 1e-12 * (magw + np.linalg.norm(vg, axis=0) * np.linalg.norm(F, axis=0))).all()
+    assert (np.abs((J * E).sum(axis=0) - w) <= 1e-12 * (magw + np.linalg.norm(J, axis=0) * np.linalg.norm(E, axis=0))).all()
+    flux = np.cross((E - E0).T, B.T).T
+    assert (np.linalg.norm(out[4:7] - flux, axis=0) <=
+            1e-12 * np.linalg.norm(E - E0, axis=0) * np.linalg.norm(B, axis=0) + 1e-300).all()
+    # no CRs in cell 7: nothing to feed back
+    assert (out[:, 7] == 0).all()
+
+
+def test_feedback_without_hall_is_the_plain_lorentz_force():
+    box, B, vg, rho, D = _feedback_cells(0, 62)
+    out = O.feedback(box, B, vg, rho, D)
+    E0 = -np.cross(vg.T, B.T).T
+    n = D[0] / 2.0 ** 40
+    J = D[1:4] / 2.0 ** 40
+    lor = n * E0 + np.cross(J.T, B.T).T
+    mag = np.abs(n) * np.linalg.norm(E0, axis=0) + np.linalg.norm(J, axis=0) * np.linalg.norm(B, axis=0)
+    assert (np.linalg.norm(-out[0:3] - lor, axis=0) <= 1e-12 * mag).all()
+    assert (np.abs(-out[3] - (J * E0).sum(axis=0)) <= 1e-12 * np.linalg.norm(J, axis=0) * np.linalg.norm(E0, axis=0)).all()
+    assert (out[4:7] == 0).all()
+
+
+def test_feedback_lambda_of_a_cold_uniform_beam():
+    """Every particle with the same velocity on a uniform lattice: u_CR is the
+    beam's u, n_CR is (q/mc) m per cell volume, and Lambda = R (u - v_g) / v_A
+    with R = n_CR / (n_g + n_CR) and v_A = |B| / sqrt(rho) (eq. lambda)."""
+    box = O.Box(ndim=2, n=(6, 5, 1), C=20.0, hall=1, qomc_gas=1.0)
+    cy, cx = np.meshgrid(np.arange(5), np.arange(6), indexing="ij")
+    ppc = 4
+    offs = [(-0.3, -0.2), (0.1, 0.35), (0.25, -0.4), (-0.45, 0.05)]
+    x = np.concatenate([np.stack([cx.ravel() + 0.5 + a, cy.ravel() + 0.5 + b, np.zeros(cx.size)])
+                        for a, b in offs], axis=1)
+    N = x.shape[1]
+    v_beam = np.array([30.0, -12.0, 6.0])
+    C = 20.0
+    gam = math.sqrt(1.0 + (v_beam ** 2).sum() / C ** 2)
+    u = v_beam / gam
+    v = np.repeat(v_beam[:, None], N, axis=1)
+    m = np.full(N, 0.002)
+    qm = np.full(N, 1.0)
+    sys = O.System(box, x, v, m, qm)
+    nc = box.n_cells
+    Bv = np.array([0.6, -0.3, 0.2])
+    B = np.repeat(Bv[:, None], nc, axis=1)
+    vgv = np.array([0.4, 0.1, -0.2])
+    vg = np.repeat(vgv[:, None], nc, axis=1)
+    rho = np.full(nc, 1.7)
+    out = sys.feedback(B, vg, rho)
+    n = ppc * 0.002
+    R = n / (1.7 + n)
+    vA = np.linalg.norm(Bv) / math.sqrt(1.7)
+    want = R * (u - vgv) / vA
+    for d in range(3):
+        assert np.allclose(out[7 + d], want[d], rtol=1e-9, atol=1e-12), (d, out[7 + d][:3], want[d])
