@@ -113,9 +113,14 @@ def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), p
                 qomc_gas=wl.box.qomc_gas, hall=wl.box.hall, frac_bits=wl.box.frac_bits,
                 max_move_cells=wl.box.max_move_cells, tile=tile)
     B, vg, rho = t(wl.B), t(wl.vg), t(wl.rho)
-    ctx = M.Context([box], [wl.N], t(wl.x), t(wl.v), t(wl.m), t(wl.qm), precision=precision)
+    xs, vs, ms_, qs = t(wl.x), t(wl.v), t(wl.m), t(wl.qm)
     torch.cuda.synchronize()
-    log(f"init done: N={wl.N} cells={box.n_cells}")
+    t_init = time.perf_counter()
+    ctx = M.Context([box], [wl.N], xs, vs, ms_, qs, precision=precision)
+    torch.cuda.synchronize()
+    init_ms = 1e3 * (time.perf_counter() - t_init)
+    del xs, vs, ms_, qs
+    log(f"init done: N={wl.N} cells={box.n_cells}, context creation {init_ms:.1f} ms")
     if warmup > 0:
         ctx.step(B, vg, rho, wl.dt, warmup)
     ctx.check()
@@ -143,7 +148,7 @@ def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), p
     D = ctx.deposit_read().cpu()
     ctx.destroy()
     return dict(ms=ms, wall_ms=1e3 * (w1 - w0), phases=phases, checksum=int(D.sum().item()),
-                n_cells=box.n_cells)
+                n_cells=box.n_cells, init_ms=init_ms)
 
 
 # --------------------------------------------------------------------------
@@ -448,6 +453,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms": phases,
+        "context_creation_ms": round(g["init_ms"], 2),
         "forms": forms,
         "hbm_frac_whole_step": round(
             (alg["per_launch"] / (ms * 1e-3 / args.steps)) / 1e9 / HBM_PEAK_GBS, 4),

@@ -420,22 +420,54 @@ int launch_push_t(mhdpic_ctx* c, hipStream_t s, bool p) {
     return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, p);
 }
 
+template <class Pol, int NDIM, int TX, int TY, int TZ>
+int launch_init_deposit_pol(mhdpic_ctx* c, hipStream_t s) {
+    constexpr int BLOCK = 256;
+    using G = Geo<Pol, NDIM, TX, TY, TZ>;
+    using R = typename Pol::R;
+    const Layout& L = c->L;
+    const size_t lds = (size_t)G::NP * 4 * 8;
+    auto kern = k_deposit_nJ_tiled<Pol, NDIM, TX, TY, TZ, BLOCK>;
+    if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s,
+                       part<typename Pol::Part, R>(c, c->cur), at<int64_t>(c, L.nJ0), L.NC,
+                       at<BoxDev>(c, L.boxes), at<WorkItem>(c, L.items[c->it]),
+                       at<uint32_t>(c, L.n_items[c->it]), at<uint32_t>(c, L.err));
+    return MHDPIC_OK;
+}
+
+template <int NDIM, int TX, int TY, int TZ>
+int launch_init_deposit_t(mhdpic_ctx* c, hipStream_t s, bool) {
+    if (c->precision == MHDPIC_FP64) return launch_init_deposit_pol<F64Pol, NDIM, TX, TY, TZ>(c, s);
+    return launch_init_deposit_pol<F32Pol, NDIM, TX, TY, TZ>(c, s);
+}
+
+// Calls F<NDIM, TX, TY, TZ>(c, s, flag) for the context's (compiled) tile.
+#define MHDPIC_TILE_DISPATCH(F, c, s, flag)                                                  \
+    do {                                                                                     \
+        const TileShape& t_ = (c)->tile;                                                     \
+        if ((c)->ndim == 2) {                                                                \
+            if (t_.x == 16 && t_.y == 16) return F<2, 16, 16, 1>(c, s, flag);               \
+            if (t_.x == 32 && t_.y == 16) return F<2, 32, 16, 1>(c, s, flag);               \
+            if (t_.x == 8 && t_.y == 8) return F<2, 8, 8, 1>(c, s, flag);                   \
+            if (t_.x == 32 && t_.y == 32) return F<2, 32, 32, 1>(c, s, flag);               \
+            if (t_.x == 64 && t_.y == 16) return F<2, 64, 16, 1>(c, s, flag);               \
+        } else {                                                                             \
+            if (t_.x == 8 && t_.y == 4 && t_.z == 4) return F<3, 8, 4, 4>(c, s, flag);      \
+            if (t_.x == 8 && t_.y == 8 && t_.z == 4) return F<3, 8, 8, 4>(c, s, flag);      \
+            if (t_.x == 4 && t_.y == 4 && t_.z == 4) return F<3, 4, 4, 4>(c, s, flag);      \
+            if (t_.x == 8 && t_.y == 8 && t_.z == 8) return F<3, 8, 8, 8>(c, s, flag);      \
+            if (t_.x == 16 && t_.y == 4 && t_.z == 4) return F<3, 16, 4, 4>(c, s, flag);    \
+        }                                                                                    \
+        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");                   \
+    } while (0)
+
+int launch_init_deposit(mhdpic_ctx* c, hipStream_t s) {
+    MHDPIC_TILE_DISPATCH(launch_init_deposit_t, c, s, false);
+}
+
 int launch_push(mhdpic_ctx* c, hipStream_t s, bool p) {
-    const TileShape& t = c->tile;
-    if (c->ndim == 2) {
-        if (t.x == 16 && t.y == 16) return launch_push_t<2, 16, 16, 1>(c, s, p);
-        if (t.x == 32 && t.y == 16) return launch_push_t<2, 32, 16, 1>(c, s, p);
-        if (t.x == 8 && t.y == 8) return launch_push_t<2, 8, 8, 1>(c, s, p);
-        if (t.x == 32 && t.y == 32) return launch_push_t<2, 32, 32, 1>(c, s, p);
-        if (t.x == 64 && t.y == 16) return launch_push_t<2, 64, 16, 1>(c, s, p);
-    } else {
-        if (t.x == 8 && t.y == 4 && t.z == 4) return launch_push_t<3, 8, 4, 4>(c, s, p);
-        if (t.x == 8 && t.y == 8 && t.z == 4) return launch_push_t<3, 8, 8, 4>(c, s, p);
-        if (t.x == 4 && t.y == 4 && t.z == 4) return launch_push_t<3, 4, 4, 4>(c, s, p);
-        if (t.x == 8 && t.y == 8 && t.z == 8) return launch_push_t<3, 8, 8, 8>(c, s, p);
-        if (t.x == 16 && t.y == 4 && t.z == 4) return launch_push_t<3, 16, 4, 4>(c, s, p);
-    }
-    return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");
+    MHDPIC_TILE_DISPATCH(launch_push_t, c, s, p);
 }
 
 int launch_bin_any(mhdpic_ctx* c, hipStream_t s, bool rekey) {
@@ -746,23 +778,8 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
         if (rc0) return cleanup(rc0);
     }
     if (L.N > 0) {
-        if (precision == MHDPIC_FP64) {
-            PartF64 P = part<PartF64, double>(c, c->cur);
-            if (ndim == 2)
-                hipLaunchKernelGGL((k_deposit_nJ_global<F64Pol, 2>), dim3(gN), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            else
-                hipLaunchKernelGGL((k_deposit_nJ_global<F64Pol, 3>), dim3(gN), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-        } else {
-            PartF32 P = part<PartF32, float>(c, c->cur);
-            if (ndim == 2)
-                hipLaunchKernelGGL((k_deposit_nJ_global<F32Pol, 2>), dim3(gN), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            else
-                hipLaunchKernelGGL((k_deposit_nJ_global<F32Pol, 3>), dim3(gN), dim3(256), 0, s, P,
-                                   at<int64_t>(c, L.nJ0), L.NC, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-        }
+        int rc0 = launch_init_deposit(c, s);
+        if (rc0) return cleanup(rc0);
     }
     INIT_TRY(hipGetLastError());
     uint32_t bits = 0;

@@ -298,62 +298,74 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     }
 }
 
-// Deposits amount V over a 3^NDIM stencil straight into global int64 arrays.
-template <class Pol, int NDIM>
-__device__ __forceinline__ void deposit_global(int64_t* dst, const BoxDev& bx, const int i[3],
-                                               const typename Pol::R wx[3],
-                                               const typename Pol::R wy[3],
-                                               const typename Pol::R wz[3], double V) {
-    using R = typename Pol::R;
-    int64_t tot = quant1(V);
-    int64_t acc = 0;
-    const int zlo = NDIM == 3 ? 0 : 1, zhi = NDIM == 3 ? 2 : 1;
-    int64_t centre = 0;
-    for (int oz = zlo; oz <= zhi; ++oz)
-        for (int oy = 0; oy < 3; ++oy)
-            for (int ox = 0; ox < 3; ++ox) {
-                int64_t g = global_cell<NDIM>(bx, i[0] + ox - 1, i[1] + oy - 1, i[2] + oz - 1);
-                if (ox == 1 && oy == 1 && oz == 1) {
-                    centre = g;
-                    continue;
-                }
-                R wxy = wx[ox] * wy[oy];
-                double W = (double)(NDIM == 3 ? wxy * wz[oz] : wxy);
-                int64_t q = quant(W, V);
-                acc += q;
-                atomicAdd((unsigned long long*)&dst[g], (unsigned long long)q);
-            }
-    atomicAdd((unsigned long long*)&dst[centre], (unsigned long long)(tot - acc));
-}
-
 // n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
-// with global atomics; used once at initialisation.
-template <class Pol, int NDIM>
-__global__ void k_deposit_nJ_global(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
-                                    const BoxDev* __restrict__ boxes,
-                                    const int64_t* __restrict__ part_off, int nb, int64_t N,
-                                    uint32_t* err) {
+// once at initialisation, on the tile-sorted particles of the first work
+// list: the same LDS box and deposit as the push's predictor, then a flush
+// with 64-bit global atomics.  The integers equal those of a particle-by-
+// particle deposit.
+template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
+                   const BoxDev* __restrict__ boxes, const WorkItem* __restrict__ items,
+                   const uint32_t* __restrict__ n_items, uint32_t* err) {
+    using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-    int i[3];
-    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-    R wx[3], wy[3], wz[3] = {R(0), R(1), R(0)};
-    Pol::weights(P.d[0][j], wx);
-    Pol::weights(P.d[1][j], wy);
-    if (NDIM == 3) Pol::weights(P.d[2][j], wz);
-    R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
-    typename Pol::K k = Pol::kin(v, bx.C, bx.C2, bx.iC);
-    double qmm = (double)P.qm[j] * (double)P.m[j];
-    double V[4] = {qmm * bx.S, (qmm * (double)k.u[0]) * bx.S, (qmm * (double)k.u[1]) * bx.S,
-                   (qmm * (double)k.u[2]) * bx.S};
-    for (int c = 0; c < 4; ++c) {
-        if (!(fabs(V[c]) < kMaxAmount)) {
-            latch(err, ERRBIT_RANGE);
-            continue;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long* Dp = reinterpret_cast<unsigned long long*>(smem);
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    const BoxDev& bx = boxes[w.box];
+    int tx, ty, tz;
+    tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
+    const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);
+    const int oz = NDIM == 3 ? tile_origin(bx, 2, tz, TZ) : 0;
+    const int sx = tile_extent(bx, 0, tx, TX), sy = tile_extent(bx, 1, ty, TY);
+    const int sz = NDIM == 3 ? tile_extent(bx, 2, tz, TZ) : 1;
+    for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
+    __syncthreads();
+    uint32_t errbits = 0;
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        int i[3];
+        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+        int lx = i[0] - ox, ly = i[1] - oy, lz = NDIM == 3 ? i[2] - oz : 0;
+        if (!(lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz)) {
+            errbits |= ERRBIT_STATE;
+            lx = min(max(lx, 0), sx - 1);
+            ly = min(max(ly, 0), sy - 1);
+            lz = NDIM == 3 ? min(max(lz, 0), sz - 1) : 0;
         }
-        deposit_global<Pol, NDIM>(nJ + c * NC, bx, i, wx, wy, wz, V[c]);
+        const int corner = G::index(lx, ly, lz) - G::CORNER;
+        R wx[3], wy[3], wz[3] = {R(0), R(1), R(0)};
+        Pol::weights(P.d[0][j], wx);
+        Pol::weights(P.d[1][j], wy);
+        if (NDIM == 3) Pol::weights(P.d[2][j], wz);
+        R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
+        typename Pol::K k = Pol::kin(v, bx.C, bx.C2, bx.iC);
+        const double qmm = (double)P.qm[j] * (double)P.m[j];
+        double V[4];
+        V[0] = qmm * bx.S;
+        V[1] = (qmm * (double)k.u[0]) * bx.S;
+        V[2] = (qmm * (double)k.u[1]) * bx.S;
+        V[3] = (qmm * (double)k.u[2]) * bx.S;
+        const bool ok = fabs(V[0]) < kMaxAmount && fabs(V[1]) < kMaxAmount &&
+                        fabs(V[2]) < kMaxAmount && fabs(V[3]) < kMaxAmount;
+        if (ok) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, corner, wx, wy, wz, V);
+        else errbits |= ERRBIT_RANGE;
+    }
+    if (errbits) latch(err, errbits);
+    __syncthreads();
+    for (int c = threadIdx.x; c < G::NP; c += BLOCK) {
+        int lx, ly, lz;
+        G::coords(c, lx, ly, lz);
+        bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
+        if (!in) continue;
+        int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            unsigned long long val = Dp[q * G::NP + c];
+            if (val) atomicAdd((unsigned long long*)&nJ[q * NC + g], val);
+        }
     }
 }
 
