@@ -87,6 +87,9 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     int64_t q = quant(W, V[c]);
+                    // keep q opaque: otherwise the compiler sums the raw fma
+                    // bits and keeps a second copy of every q for the atomic
+                    asm("" : "+v"(q));
                     acc[c] += q;
                     atomicAdd(p + c * NB, (unsigned long long)q);
                 }
