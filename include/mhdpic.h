@@ -63,7 +63,7 @@ enum {
                                beyond the library's index limits */
     MHDPIC_ENONFINITE = -5, /* a position or velocity is not finite */
     MHDPIC_ESTATE = -6,     /* internal consistency check failed */
-    MHDPIC_ENOTSUP = -7     /* configuration not supported by this build */
+    MHDPIC_ENOTSUP = -7     /* a configuration the compiled library does not cover */
 };
 
 enum { MHDPIC_FP64 = 0, MHDPIC_FP32_MIXED = 1 };
