@@ -77,24 +77,66 @@ __device__ __forceinline__ int source_tile(const BoxDev& bx, int d, int k) {
     return bx.tile_off + (sz * bx.nt[1] + sy) * bx.nt[0] + sx;
 }
 
-// Per destination tile: particles arriving from the (item, code) groups of
-// the current work list, and the number of next-step work items.
+// The groups arriving at destination tile d, in order (code by code, and
+// within a code the source tile's items in order), spread over the lanes of
+// one wave: lane k < K holds code k's first source item and its number of
+// items, and group g of the list is code k_of(g), item i_of(g).
 template <int NDIM>
-__global__ void k_bin_count(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
-                            const int32_t* __restrict__ tile_box, const BoxDev* __restrict__ boxes,
-                            uint32_t* __restrict__ tile_count, uint32_t* __restrict__ tile_items,
-                            int NT, int P) {
-    constexpr int K = Codes<NDIM>::K;
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= NT) return;
-    const BoxDev& bx = boxes[tile_box[d]];
-    uint32_t tot = 0;
-    for (int k = 0; k < K; ++k) {
-        int s = source_tile<NDIM>(bx, d, k);
-        for (uint32_t i = item_first[s]; i < item_first[s + 1]; ++i) tot += cnt[(size_t)i * K + k];
+struct TileGroups {
+    static constexpr int K = Codes<NDIM>::K;
+    uint32_t i0, pre, total;  // lane k: first item of code k, groups before code k
+    __device__ __forceinline__ void load(const BoxDev& bx, int d, const uint32_t* item_first,
+                                         int lane) {
+        uint32_t n = 0;
+        i0 = 0;
+        if (lane < K) {
+            const int s = source_tile<NDIM>(bx, d, lane);
+            i0 = item_first[s];
+            n = item_first[s + 1] - i0;
+        }
+        uint32_t x = n;  // inclusive scan over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        pre = x - n;
+        total = __shfl(x, 63);
     }
-    tile_count[d] = tot;
-    tile_items[d] = (tot + (uint32_t)P - 1) / (uint32_t)P;
+    // code and item of group g (g < total); every lane of the wave calls it
+    __device__ __forceinline__ void group(uint32_t g, int& k, uint32_t& item) const {
+        k = 0;
+        for (int q = 1; q < K; ++q)
+            if ((uint32_t)__shfl(pre, q) <= g) k = q;
+        item = (uint32_t)__shfl(i0, k) + (g - (uint32_t)__shfl(pre, k));
+    }
+};
+
+// Per destination tile: particles arriving from the (item, code) groups of
+// the current work list, and the number of next-step work items.  One wave
+// per tile.
+template <int NDIM>
+__global__ void __launch_bounds__(256)
+k_bin_count(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
+            const int32_t* __restrict__ tile_box, const BoxDev* __restrict__ boxes,
+            uint32_t* __restrict__ tile_count, uint32_t* __restrict__ tile_items, int NT, int P) {
+    constexpr int K = Codes<NDIM>::K;
+    const int lane = threadIdx.x & 63;
+    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (d >= NT) return;  // whole wave
+    TileGroups<NDIM> tg;
+    tg.load(boxes[tile_box[d]], d, item_first, lane);
+    uint32_t tot = 0;
+    for (uint32_t g0 = 0; g0 < tg.total; g0 += 64) {  // the same trip count in every lane
+        int k;
+        uint32_t i;
+        tg.group(g0 + lane, k, i);
+        if (g0 + lane < tg.total) tot += cnt[(size_t)i * K + k];
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (lane == 0) {
+        tile_count[d] = tot;
+        tile_items[d] = (tot + (uint32_t)P - 1) / (uint32_t)P;
+    }
 }
 
 // One block: exclusive scans of tile_count (-> start) and tile_items
@@ -137,36 +179,47 @@ k_scan2(const uint32_t* __restrict__ tile_count, const uint32_t* __restrict__ ti
     }
 }
 
-// Per destination tile: the offset of every arriving (item, code) group and
-// the tile's next-step work items.
+// Per destination tile: the offset of every arriving (item, code) group, in
+// the order of TileGroups, and the tile's next-step work items.  One wave per
+// tile; group counts are scanned across the wave.
 template <int NDIM>
-__global__ void k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
-                              uint32_t* __restrict__ off, const int32_t* __restrict__ tile_box,
-                              const BoxDev* __restrict__ boxes, const uint32_t* __restrict__ start,
-                              const uint32_t* __restrict__ item_first_next,
-                              WorkItem* __restrict__ items_next, int NT, int P) {
+__global__ void __launch_bounds__(256)
+k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ item_first,
+              uint32_t* __restrict__ off, const int32_t* __restrict__ tile_box,
+              const BoxDev* __restrict__ boxes, const uint32_t* __restrict__ start,
+              const uint32_t* __restrict__ item_first_next,
+              WorkItem* __restrict__ items_next, int NT, int P) {
     constexpr int K = Codes<NDIM>::K;
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= NT) return;
-    const BoxDev& bx = boxes[tile_box[d]];
+    const int lane = threadIdx.x & 63;
+    const int d = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (d >= NT) return;  // whole wave
+    TileGroups<NDIM> tg;
+    tg.load(boxes[tile_box[d]], d, item_first, lane);
     const uint32_t s0 = start[d];
     uint32_t run = s0;
-    for (int k = 0; k < K; ++k) {
-        int s = source_tile<NDIM>(bx, d, k);
-        for (uint32_t i = item_first[s]; i < item_first[s + 1]; ++i) {
-            off[(size_t)i * K + k] = run;
-            run += cnt[(size_t)i * K + k];
+    for (uint32_t g0 = 0; g0 < tg.total; g0 += 64) {  // the same trip count in every lane
+        int k;
+        uint32_t i;
+        tg.group(g0 + lane, k, i);
+        const bool in = g0 + lane < tg.total;
+        const uint32_t c = in ? cnt[(size_t)i * K + k] : 0u;
+        uint32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
         }
+        if (in) off[(size_t)i * K + k] = run + x - c;
+        run += __shfl(x, 63);
     }
     const uint32_t c = run - s0;
-    uint32_t io = item_first_next[d];
-    for (uint32_t q = 0; q < c; q += (uint32_t)P) {
+    const uint32_t io = item_first_next[d];
+    for (uint32_t q = (uint32_t)lane; q * (uint32_t)P < c; q += 64) {
         WorkItem w;
         w.tile = d;
-        w.begin = (int32_t)(s0 + q);
-        w.end = (int32_t)(s0 + min(q + (uint32_t)P, c));
+        w.begin = (int32_t)(s0 + q * (uint32_t)P);
+        w.end = (int32_t)(s0 + min((q + 1) * (uint32_t)P, c));
         w.box = tile_box[d];
-        items_next[io++] = w;
+        items_next[io + q] = w;
     }
 }
 

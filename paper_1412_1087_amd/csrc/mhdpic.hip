@@ -329,7 +329,7 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
         hipLaunchKernelGGL((k_rekey_items<Pol, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
                            at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
                            at<uint32_t>(c, L.n_items[it]), bd, T3, at<uint32_t>(c, L.err));
-    const unsigned gT = grid_for(L.NT, 256);
+    const unsigned gT = grid_for(L.NT, 4);  // one wave per tile, 4 waves per block
     hipLaunchKernelGGL(k_bin_count<NDIM>, dim3(gT), dim3(256), 0, s, at<uint32_t>(c, L.cnt),
                        at<uint32_t>(c, L.item_first[it]), at<int32_t>(c, L.tile_box), bd,
                        at<uint32_t>(c, L.count), at<uint32_t>(c, L.cursor), L.NT, kItemParticles);
