@@ -254,11 +254,28 @@ struct Rec {
     }
 };
 
-template <typename T>
+// Moves one array of an item: a coalesced load of the item into LDS, then
+// destination-ordered reads from LDS and coalesced stores.  Every thread of
+// the block calls it.
+template <int BLOCK, typename T>
 __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restrict__ dst,
                                            const uint16_t* from, const uint32_t* to, int begin,
-                                           int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[to[i]] = src[begin + from[i]];
+                                           int n, T* stage) {
+    constexpr int U = kItemParticles / BLOCK;
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = threadIdx.x + u * BLOCK;
+        if (i < n) v[u] = src[begin + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = threadIdx.x + u * BLOCK;
+        if (i < n) stage[i] = v[u];
+    }
+    __syncthreads();
+    for (int L = threadIdx.x; L < n; L += BLOCK) dst[to[L]] = stage[from[L]];
+    __syncthreads();
 }
 
 // Moves the particles of each current work item to their groups' offsets
@@ -275,7 +292,8 @@ __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restr
 //
 // Pass 1 ranks every particle within its (group, residue) by an LDS counter;
 // pass 2 turns the ranks into an LDS map from destination to source, and the
-// particles are moved one array at a time in destination order.
+// particles are moved one array at a time: loaded in source order into LDS,
+// stored in destination order.
 template <int NDIM, typename PS, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
@@ -289,6 +307,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     __shared__ uint32_t s_base[NG], s_lbase[NG];
     __shared__ uint32_t s_key[kItemParticles];
     __shared__ uint16_t s_src[kItemParticles];
+    __shared__ typename PS::R s_stage[kItemParticles];
     uint32_t item;
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
@@ -339,16 +358,20 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         s_key[L] = s_base[g] + ((uint32_t)L - s_lbase[g]);
     }
     __syncthreads();
-    // one array at a time, in destination order
+    // one array at a time, through LDS, in destination order
+    using R = typename PS::R;
     const int n = w.end - w.begin;
-    move_array(A.cell, Bo.cell, s_src, s_key, w.begin, n);
+    R* stR = reinterpret_cast<R*>(s_stage);
+    uint32_t* stU = reinterpret_cast<uint32_t*>(s_stage);
+    int32_t* stI = reinterpret_cast<int32_t*>(s_stage);
+    move_array<BLOCK>(A.cell, Bo.cell, s_src, s_key, w.begin, n, stU);
 #pragma unroll
-    for (int q = 0; q < NDIM; ++q) move_array(A.d[q], Bo.d[q], s_src, s_key, w.begin, n);
+    for (int q = 0; q < NDIM; ++q) move_array<BLOCK>(A.d[q], Bo.d[q], s_src, s_key, w.begin, n, stR);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) move_array(A.v[q], Bo.v[q], s_src, s_key, w.begin, n);
-    move_array(A.m, Bo.m, s_src, s_key, w.begin, n);
-    move_array(A.qm, Bo.qm, s_src, s_key, w.begin, n);
-    move_array(A.pid, Bo.pid, s_src, s_key, w.begin, n);
+    for (int q = 0; q < 3; ++q) move_array<BLOCK>(A.v[q], Bo.v[q], s_src, s_key, w.begin, n, stR);
+    move_array<BLOCK>(A.m, Bo.m, s_src, s_key, w.begin, n, stR);
+    move_array<BLOCK>(A.qm, Bo.qm, s_src, s_key, w.begin, n, stR);
+    move_array<BLOCK>(A.pid, Bo.pid, s_src, s_key, w.begin, n, stI);
 }
 
 // Moves the particles of each current work item to their groups' offsets
