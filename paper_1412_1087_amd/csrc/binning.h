@@ -223,44 +223,13 @@ k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ ite
     }
 }
 
-// One particle's record, held in registers while it is moved.
-template <int NDIM, typename PS>
-struct Rec {
-    using R = typename PS::R;
-    uint32_t cell;
-    R d[NDIM];
-    R v[3];
-    R m, qm;
-    int32_t pid;
-    __device__ __forceinline__ void load(const PS& A, int j) {
-        cell = A.cell[j];
-#pragma unroll
-        for (int q = 0; q < NDIM; ++q) d[q] = A.d[q][j];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) v[q] = A.v[q][j];
-        m = A.m[j];
-        qm = A.qm[j];
-        pid = A.pid[j];
-    }
-    __device__ __forceinline__ void store(const PS& B, uint32_t s) const {
-        B.cell[s] = cell;
-#pragma unroll
-        for (int q = 0; q < NDIM; ++q) B.d[q][s] = d[q];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) B.v[q][s] = v[q];
-        B.m[s] = m;
-        B.qm[s] = qm;
-        B.pid[s] = pid;
-    }
-};
-
 // Moves one array of an item: a coalesced load of the item into LDS, then
 // destination-ordered reads from LDS and coalesced stores.  Every thread of
 // the block calls it.
 template <int BLOCK, typename T>
 __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restrict__ dst,
-                                           const uint16_t* from, const uint32_t* to, int begin,
-                                           int n, T* stage) {
+                                           const uint16_t* from, const uint8_t* grp,
+                                           const uint32_t* goff, int begin, int n, T* stage) {
     constexpr int U = kItemParticles / BLOCK;
     T v[U];
 #pragma unroll
@@ -274,12 +243,11 @@ __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restr
         if (i < n) stage[i] = v[u];
     }
     __syncthreads();
-    for (int L = threadIdx.x; L < n; L += BLOCK) dst[to[L]] = stage[from[L]];
+    for (int L = threadIdx.x; L < n; L += BLOCK) dst[goff[grp[L]] + (uint32_t)L] = stage[from[L]];
     __syncthreads();
 }
 
-// Moves the particles of each current work item to their groups' offsets
-// (3D; the 2D binning uses k_bin_scatter_chunk).
+// Moves the particles of each current work item to their groups' offsets.
 //
 // Order within a group (the particles of one item with one direction code):
 // the particles that stay in the tile are grouped by the class of their
@@ -304,10 +272,11 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     constexpr int NG = NCL + K;   // groups: stay classes, then moving codes
     constexpr int RS = kResidues;
     __shared__ uint32_t s_n[NG * RS];
-    __shared__ uint32_t s_base[NG], s_lbase[NG];
-    __shared__ uint32_t s_key[kItemParticles];
+    __shared__ uint32_t s_off[NG], s_lbase[NG];
     __shared__ uint16_t s_src[kItemParticles];
+    __shared__ uint8_t s_grp[kItemParticles];
     __shared__ typename PS::R s_stage[kItemParticles];
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(s_stage);  // ranks, until the moves
     uint32_t item;
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
@@ -333,7 +302,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         } else {
             base = off[(size_t)item * K + (g - NCL)];
         }
-        s_base[g] = base;
+        s_off[g] = base - lb;  // destination of local slot L of group g: s_off[g] + L
         s_lbase[g] = lb;
     }
     __syncthreads();
@@ -349,13 +318,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
             pos += min(nq, r) + ((q < b && nq > r) ? 1u : 0u);
         }
         s_src[s_lbase[g] + pos] = (uint16_t)(j - w.begin);
-    }
-    __syncthreads();
-    // destination slot of every local slot (groups in order)
-    for (int L = threadIdx.x; L < w.end - w.begin; L += BLOCK) {
-        int g = 0;
-        while (g + 1 < NG && s_lbase[g + 1] <= (uint32_t)L) ++g;
-        s_key[L] = s_base[g] + ((uint32_t)L - s_lbase[g]);
+        s_grp[s_lbase[g] + pos] = (uint8_t)g;
     }
     __syncthreads();
     // one array at a time, through LDS, in destination order
@@ -364,86 +327,14 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     R* stR = reinterpret_cast<R*>(s_stage);
     uint32_t* stU = reinterpret_cast<uint32_t*>(s_stage);
     int32_t* stI = reinterpret_cast<int32_t*>(s_stage);
-    move_array<BLOCK>(A.cell, Bo.cell, s_src, s_key, w.begin, n, stU);
+    move_array<BLOCK>(A.cell, Bo.cell, s_src, s_grp, s_off, w.begin, n, stU);
 #pragma unroll
-    for (int q = 0; q < NDIM; ++q) move_array<BLOCK>(A.d[q], Bo.d[q], s_src, s_key, w.begin, n, stR);
+    for (int q = 0; q < NDIM; ++q) move_array<BLOCK>(A.d[q], Bo.d[q], s_src, s_grp, s_off, w.begin, n, stR);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) move_array<BLOCK>(A.v[q], Bo.v[q], s_src, s_key, w.begin, n, stR);
-    move_array<BLOCK>(A.m, Bo.m, s_src, s_key, w.begin, n, stR);
-    move_array<BLOCK>(A.qm, Bo.qm, s_src, s_key, w.begin, n, stR);
-    move_array<BLOCK>(A.pid, Bo.pid, s_src, s_key, w.begin, n, stI);
-}
-
-// Moves the particles of each current work item to their groups' offsets
-// (2D).  The item is moved in chunks of one particle per thread.  Within a
-// chunk, each group's particles are laid out level by level (the r-th
-// particle of every bank residue present, in residue order), so 16
-// consecutive particles fall on distinct LDS bank pairs while the stores of a
-// chunk stay within a window of the chunk's size.  The next chunk's records
-// are loaded before the current chunk is stored.  In 2D the push gains less
-// from whole-group ordering than such an ordering costs in scattered stores.
-template <int NDIM, typename PS, int BLOCK>
-__global__ void __launch_bounds__(BLOCK)
-k_bin_scatter_chunk(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
-                    const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
-    constexpr int K = Codes<NDIM>::K;
-    constexpr int RS = kResidues;
-    __shared__ uint32_t s_n[K * RS];
-    __shared__ uint32_t s_run[K];
-    uint32_t item;
-    if (!item_of_block(n_items, item)) return;
-    const WorkItem w = items[item];
-    for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
-    for (int c = threadIdx.x; c < K; c += BLOCK) s_run[c] = off[(size_t)item * K + c];
-    __syncthreads();
-    Rec<NDIM, PS> cur;
-    uint32_t cr = 0;
-    bool act = w.begin + (int)threadIdx.x < w.end;
-    if (act) {
-        cr = code[w.begin + threadIdx.x];
-        cur.load(A, w.begin + threadIdx.x);
-    }
-    for (int base = w.begin; base < w.end; base += BLOCK) {
-        const int k = code_dir(cr), b = code_residue(cr);
-        uint32_t lev = 0;
-        if (act) lev = atomicAdd(&s_n[k * RS + b], 1u);
-        __syncthreads();
-        uint32_t s = 0;
-        if (act) {
-            const uint32_t* nk = s_n + k * RS;
-            uint32_t pos = 0;
-#pragma unroll
-            for (int q = 0; q < RS; ++q) {
-                uint32_t nq = nk[q];
-                pos += min(nq, lev) + ((q < b && nq > lev) ? 1u : 0u);
-            }
-            s = s_run[k] + pos;
-        }
-        __syncthreads();
-        // advance the group bases by this chunk's counts and clear them
-        for (int c = threadIdx.x; c < K; c += BLOCK) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int q = 0; q < RS; ++q) t += s_n[c * RS + q];
-            s_run[c] += t;
-        }
-        __syncthreads();
-        for (int c = threadIdx.x; c < K * RS; c += BLOCK) s_n[c] = 0;
-        // prefetch the next chunk, then store this one
-        const int jn = base + BLOCK + (int)threadIdx.x;
-        const bool actn = jn < w.end;
-        Rec<NDIM, PS> nxt;
-        uint32_t crn = 0;
-        if (actn) {
-            crn = code[jn];
-            nxt.load(A, jn);
-        }
-        if (act) cur.store(Bo, s);
-        cur = nxt;
-        cr = crn;
-        act = actn;
-        __syncthreads();
-    }
+    for (int q = 0; q < 3; ++q) move_array<BLOCK>(A.v[q], Bo.v[q], s_src, s_grp, s_off, w.begin, n, stR);
+    move_array<BLOCK>(A.m, Bo.m, s_src, s_grp, s_off, w.begin, n, stR);
+    move_array<BLOCK>(A.qm, Bo.qm, s_src, s_grp, s_off, w.begin, n, stR);
+    move_array<BLOCK>(A.pid, Bo.pid, s_src, s_grp, s_off, w.begin, n, stI);
 }
 
 // Initial sort: key = tile of the particle's current cell (any tile), with

@@ -341,14 +341,9 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
                        at<int32_t>(c, L.tile_box), bd, at<uint32_t>(c, L.start),
                        at<uint32_t>(c, L.item_first[1 - it]), at<WorkItem>(c, L.items[1 - it]),
                        L.NT, kItemParticles);
-    if constexpr (NDIM == 3)
-        hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256>), dim3(item_grid(L)), dim3(256), 0, s, A,
-                           Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
-                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
-    else
-        hipLaunchKernelGGL((k_bin_scatter_chunk<NDIM, PS, 256>), dim3(item_grid(L)), dim3(256), 0, s, A,
-                           Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
-                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
+    hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256>), dim3(item_grid(L)), dim3(256), 0, s, A, Bo,
+                       at<uint16_t>(c, L.code), at<uint32_t>(c, L.off), at<WorkItem>(c, L.items[it]),
+                       at<uint32_t>(c, L.n_items[it]));
     c->cur = 1 - c->cur;
     c->it = 1 - it;
     return MHDPIC_OK;
