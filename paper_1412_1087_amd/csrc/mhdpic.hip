@@ -385,7 +385,8 @@ int launch_initial_sort_any(mhdpic_ctx* c, hipStream_t s) {
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
 int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
-    constexpr int BLOCK = 256;
+    // 2D: two blocks of eight waves fill a CU (four waves per SIMD) within the LDS
+    constexpr int BLOCK = NDIM == 2 ? 512 : 256;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     const Layout& L = c->L;
