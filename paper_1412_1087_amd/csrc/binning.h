@@ -223,27 +223,48 @@ k_bin_offsets(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ ite
     }
 }
 
-// Moves one array of an item: a coalesced load of the item into LDS, then
-// destination-ordered reads from LDS and coalesced stores.  Every thread of
-// the block calls it.
+// Moving the arrays of one item through LDS: each array is loaded in source
+// order (coalesced) into registers, written to an LDS staging buffer, and
+// stored in destination order (coalesced).  The next array's loads are issued
+// while the current one is being stored.
+struct MoveMap {
+    const uint16_t* from;  // local slot -> source index in the item
+    const uint8_t* grp;    // local slot -> group
+    const uint32_t* goff;  // group -> destination of local slot 0
+    int begin, n;
+};
+
 template <int BLOCK, typename T>
-__device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restrict__ dst,
-                                           const uint16_t* from, const uint8_t* grp,
-                                           const uint32_t* goff, int begin, int n, T* stage) {
-    constexpr int U = kItemParticles / BLOCK;
+struct ItemRegs {  // this thread's elements threadIdx.x + u*BLOCK of one array
+    static constexpr int U = kItemParticles / BLOCK;
     T v[U];
+    __device__ __forceinline__ void load(const T* __restrict__ src, const MoveMap& mm) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int i = threadIdx.x + u * BLOCK;
-        if (i < n) v[u] = src[begin + i];
+        for (int u = 0; u < U; ++u) {
+            const int i = threadIdx.x + u * BLOCK;
+            if (i < mm.n) v[u] = src[mm.begin + i];
+        }
     }
+    __device__ __forceinline__ void stage(T* st, const MoveMap& mm) const {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int i = threadIdx.x + u * BLOCK;
-        if (i < n) stage[i] = v[u];
+        for (int u = 0; u < U; ++u) {
+            const int i = threadIdx.x + u * BLOCK;
+            if (i < mm.n) st[i] = v[u];
+        }
     }
+};
+
+// Stages `cur`, then stores it in destination order while `nxt` (if given)
+// is loaded.  Every thread of the block calls it.
+template <int BLOCK, typename TC, typename TN>
+__device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __restrict__ dst,
+                                          void* stage, ItemRegs<BLOCK, TN>& nxt,
+                                          const TN* __restrict__ nsrc, const MoveMap& mm) {
+    TC* st = reinterpret_cast<TC*>(stage);
+    cur.stage(st, mm);
     __syncthreads();
-    for (int L = threadIdx.x; L < n; L += BLOCK) dst[goff[grp[L]] + (uint32_t)L] = stage[from[L]];
+    if (nsrc) nxt.load(nsrc, mm);
+    for (int L = threadIdx.x; L < mm.n; L += BLOCK) dst[mm.goff[mm.grp[L]] + (uint32_t)L] = st[mm.from[L]];
     __syncthreads();
 }
 
@@ -260,8 +281,7 @@ __device__ __forceinline__ void move_array(const T* __restrict__ src, T* __restr
 //
 // Pass 1 ranks every particle within its (group, residue) by an LDS counter;
 // pass 2 turns the ranks into an LDS map from destination to source, and the
-// particles are moved one array at a time: loaded in source order into LDS,
-// stored in destination order.
+// particles are moved one array at a time through LDS (MoveMap, move_step).
 template <int NDIM, typename PS, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
@@ -321,20 +341,36 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         s_grp[s_lbase[g] + pos] = (uint8_t)g;
     }
     __syncthreads();
-    // one array at a time, through LDS, in destination order
+    // the arrays one after another, through LDS, in destination order
     using R = typename PS::R;
-    const int n = w.end - w.begin;
-    R* stR = reinterpret_cast<R*>(s_stage);
-    uint32_t* stU = reinterpret_cast<uint32_t*>(s_stage);
-    int32_t* stI = reinterpret_cast<int32_t*>(s_stage);
-    move_array<BLOCK>(A.cell, Bo.cell, s_src, s_grp, s_off, w.begin, n, stU);
+    constexpr int NR = NDIM + 5;  // offsets, four-velocity, m, q/m
+    const MoveMap mm{s_src, s_grp, s_off, w.begin, w.end - w.begin};
+    const R* rsrc[NR];
+    R* rdst[NR];
 #pragma unroll
-    for (int q = 0; q < NDIM; ++q) move_array<BLOCK>(A.d[q], Bo.d[q], s_src, s_grp, s_off, w.begin, n, stR);
+    for (int q = 0; q < NDIM; ++q) {
+        rsrc[q] = A.d[q];
+        rdst[q] = Bo.d[q];
+    }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) move_array<BLOCK>(A.v[q], Bo.v[q], s_src, s_grp, s_off, w.begin, n, stR);
-    move_array<BLOCK>(A.m, Bo.m, s_src, s_grp, s_off, w.begin, n, stR);
-    move_array<BLOCK>(A.qm, Bo.qm, s_src, s_grp, s_off, w.begin, n, stR);
-    move_array<BLOCK>(A.pid, Bo.pid, s_src, s_grp, s_off, w.begin, n, stI);
+    for (int q = 0; q < 3; ++q) {
+        rsrc[NDIM + q] = A.v[q];
+        rdst[NDIM + q] = Bo.v[q];
+    }
+    rsrc[NDIM + 3] = A.m;
+    rdst[NDIM + 3] = Bo.m;
+    rsrc[NDIM + 4] = A.qm;
+    rdst[NDIM + 4] = Bo.qm;
+    ItemRegs<BLOCK, uint32_t> rcell;
+    ItemRegs<BLOCK, int32_t> rpid;
+    ItemRegs<BLOCK, R> rbuf[2];
+    rcell.load(A.cell, mm);
+    move_step<BLOCK>(rcell, Bo.cell, s_stage, rbuf[0], rsrc[0], mm);
+#pragma unroll
+    for (int q = 0; q + 1 < NR; ++q)
+        move_step<BLOCK>(rbuf[q & 1], rdst[q], s_stage, rbuf[(q + 1) & 1], rsrc[q + 1], mm);
+    move_step<BLOCK>(rbuf[(NR - 1) & 1], rdst[NR - 1], s_stage, rpid, A.pid, mm);
+    move_step<BLOCK>(rpid, Bo.pid, s_stage, rcell, (const uint32_t*)nullptr, mm);
 }
 
 // Initial sort: key = tile of the particle's current cell (any tile), with
