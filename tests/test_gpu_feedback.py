@@ -45,10 +45,10 @@ def test_feedback_of_boxes_with_and_without_hall():
     wb.box.hall = 1
     g = GpuRun([wa, wb])
     out = g.ctx.feedback(g.B, g.vg, g.rho).cpu().numpy()
-    D = g.deposits()
     for b, w in enumerate([wa, wb]):
         sl = slice(g.cell_off[b], g.cell_off[b + 1])
-        want = O.feedback(oracle_box(w.box), w.B, w.vg, w.rho, D[b])
+        o = oracle_run(w)                      # the oracle's own initial n_CR, J_CR
+        want = O.feedback(oracle_box(w.box), w.B, w.vg, w.rho, o.D)
         assert (out[:, sl] == want).all(), b
     sla = slice(g.cell_off[0], g.cell_off[1])
     assert (out[4:7, sla] == 0).all()

@@ -81,3 +81,39 @@ def test_subcycled_step_checks_its_arguments():
     g.step(1, dts=[big], n_sub=3)      # over the limit as one step, within it as three
     o.step(wl.B, wl.vg, wl.rho, big, 1, n_sub=3)
     _compare(wl, g, o, "large dt in 3 sub-steps")
+
+
+def test_subcycled_precision_form_equals_its_plain_substeps():
+    """Without the Hall term the field does not depend on n_CR, J_CR, so a
+    sub-cycled step of the precision form equals its own plain steps of
+    dt/n_sub bit for bit (the same kernels on the same binary32 states)."""
+    _need_gpu()
+    wl = W.gyro2d(nx=36, ny=20, ppc=6, seed=1230)
+    a = GpuRun(wl, precision=1)
+    b = GpuRun(wl, precision=1)
+    a.step(2, n_sub=3)
+    for _ in range(6):
+        b.step(1, dts=[wl.dt / 3])
+    (Da,) = a.deposits()
+    (Db,) = b.deposits()
+    assert (Da == Db).all()
+    ((xa, va),) = a.particles()
+    ((xb, vb),) = b.particles()
+    assert (va == vb).all() and (xa == xb).all()
+
+
+def test_subcycled_multi_box_context_equals_single_boxes():
+    _need_gpu()
+    wls = [W.gyro2d(nx=20 + 6 * k, ny=18, ppc=3 + k, seed=1240 + k) for k in range(3)]
+    wls[1].box.hall = 1
+    many = GpuRun(wls)
+    many.step(2, n_sub=4)
+    Dm = many.deposits()
+    Pm = many.particles()
+    for k, w in enumerate(wls):
+        one = GpuRun(w)
+        one.step(2, n_sub=4)
+        (D1,) = one.deposits()
+        ((x1, v1),) = one.particles()
+        assert (Dm[k] == D1).all(), k
+        assert (Pm[k][1] == v1).all(), k
