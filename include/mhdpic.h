@@ -152,7 +152,8 @@ int mhdpic_feedback(mhdpic_ctx* ctx, const double* B, const double* vg, const do
                     double* out, void* hip_stream);
 
 /* mhdpic_step through a HIP graph./* mhdpic_step through a HIP graph.  The first call (and any call whose
- * B, vg, rho, dt or n_steps differ from the cached ones) captures the n_steps
+ * B, vg, rho, dt or n_steps differ from the cached ones, or that finds the
+ * context's buffers in another state than at capture) captures the n_steps
  * steps into a graph owned by the context; every call then launches that
  * graph, so one launch advances all boxes n_steps steps.  n_steps must be even
  * (the step's buffer swaps then return to the captured state after each
@@ -160,6 +161,13 @@ int mhdpic_feedback(mhdpic_ctx* ctx, const double* B, const double* vg, const do
  * when it captures.  Does not wait otherwise. */
 int mhdpic_step_graph(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
                       const double* dt, int32_t n_steps, void* hip_stream);
+
+/* mhdpic_step_graph with particle sub-cycling (see mhdpic_step_sub): each of
+ * the n_steps steps (n_steps even) takes n_sub particle steps of dt/n_sub.
+ * The cached graph is also recaptured when n_sub changes, or when eager calls
+ * in between left the context's buffers in another state. */
+int mhdpic_step_graph_sub(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
+                          const double* dt, int32_t n_steps, int32_t n_sub, void* hip_stream);
 
 /* Picks the tile shape (cells per tile, the LDS staging unit of the push
  * kernel) with the shortest step time for this workload: for every compiled

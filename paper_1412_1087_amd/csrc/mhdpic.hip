@@ -98,14 +98,18 @@ struct Layout {
     size_t total = 0;
 };
 
+// What a captured graph depends on: its arguments and the buffer state it was
+// captured in (which particle, work-list and n, J buffers are current).
 struct GraphKey {
     const double* B = nullptr;
     const double* vg = nullptr;
     const double* rho = nullptr;
-    int32_t n_steps = 0;
+    int32_t n_steps = 0, n_sub = 1;
     std::vector<double> dt;
+    int cur = 0, it = 0, nj = 0;
     bool operator==(const GraphKey& o) const {
-        return B == o.B && vg == o.vg && rho == o.rho && n_steps == o.n_steps && dt == o.dt;
+        return B == o.B && vg == o.vg && rho == o.rho && n_steps == o.n_steps && n_sub == o.n_sub &&
+               dt == o.dt && cur == o.cur && it == o.it && nj == o.nj;
     }
 };
 
@@ -818,7 +822,12 @@ int mhdpic_step_sub(mhdpic_ctx* c, const double* B, const double* vg, const doub
 
 int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
                       const double* dt, int32_t n_steps, void* hip_stream) {
-    int rc = check_step_args(c, B, vg, rho, dt, n_steps, 1);
+    return mhdpic_step_graph_sub(c, B, vg, rho, dt, n_steps, 1, hip_stream);
+}
+
+int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                          const double* dt, int32_t n_steps, int32_t n_sub, void* hip_stream) {
+    int rc = check_step_args(c, B, vg, rho, dt, n_steps, n_sub);
     if (rc) return rc;
     if (n_steps <= 0 || n_steps % 2) return fail(MHDPIC_EINVAL, "n_steps must be even and > 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -826,16 +835,18 @@ int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const do
     rc = poll_error(c);
     if (rc) return rc;
     c->last_stream = s;
-    GraphKey key{B, vg, rho, n_steps, std::vector<double>(dt, dt + c->nb)};
+    // the step constants live in device memory that the graph reads: bring
+    // them to this dt first (a no-op when they are current)
+    rc = set_dt(c, dt, n_sub, s, false);
+    if (rc) return rc;
+    GraphKey key{B, vg, rho, n_steps, n_sub, std::vector<double>(dt, dt + c->nb), c->cur, c->it, c->nj};
     if (!c->graph_exec || !(c->graph_key == key)) {
         if (c->graph_exec) {
             HIP_TRY(hipGraphExecDestroy(c->graph_exec));
             c->graph_exec = nullptr;
         }
-        rc = set_dt(c, dt, 1, s, false);  // uploads happen outside the graph
-        if (rc) return rc;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_steps(c, B, vg, rho, n_steps, 1, s, false);
+        rc = enqueue_steps(c, B, vg, rho, n_steps, n_sub, s, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (rc) {
@@ -849,7 +860,7 @@ int mhdpic_step_graph(mhdpic_ctx* c, const double* B, const double* vg, const do
             c->graph_exec = nullptr;
             return fail(MHDPIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
-        c->graph_key = key;
+        c->graph_key = key;  // n_steps is even: the buffers end as they began
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, s));
     return post_error_copy(c, s);

@@ -25,7 +25,7 @@ EXPORTED = [
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
-    "mhdpic_feedback",
+    "mhdpic_feedback", "mhdpic_step_graph_sub",
 ]
 
 
@@ -64,6 +64,9 @@ def lib():
         L.mhdpic_step_sub.restype = ct.c_int
         L.mhdpic_step_sub.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32,
                                       ct.c_int32, vp]
+        L.mhdpic_step_graph_sub.restype = ct.c_int
+        L.mhdpic_step_graph_sub.argtypes = [vp, vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32,
+                                            ct.c_int32, vp]
         L.mhdpic_feedback.restype = ct.c_int
         L.mhdpic_feedback.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mhdpic_deposit_read.restype = ct.c_int
@@ -206,13 +209,18 @@ class Context:
                                          int(n_sub), _stream(stream)))
 
     def step_graph(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor | None, dt,
-                   n_steps: int, stream):
-        """n_steps (even) steps as one cached HIP graph launch on a non-default stream."""
+                   n_steps: int, stream, n_sub: int = 1):
+        """n_steps (even) steps as one cached HIP graph launch on a non-default
+        stream; with n_sub > 1 each step takes n_sub particle sub-steps."""
         if isinstance(dt, (int, float)):
             dt = [float(dt)] * len(self.boxes)
         dts = (ct.c_double * len(self.boxes))(*[float(a) for a in dt])
-        _check(lib().mhdpic_step_graph(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
-                                       _stream(stream)))
+        if n_sub == 1:
+            _check(lib().mhdpic_step_graph(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts,
+                                           int(n_steps), _stream(stream)))
+        else:
+            _check(lib().mhdpic_step_graph_sub(self._h, _ptr(B), _ptr(vg), _ptr(rho), dts,
+                                               int(n_steps), int(n_sub), _stream(stream)))
 
     def feedback(self, B: torch.Tensor, vg: torch.Tensor, rho: torch.Tensor,
                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -98,3 +98,53 @@ def test_autotune_picks_a_compiled_shape_that_stays_exact():
     o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
     (D,) = g.deposits()
     assert (D == o.D).all()
+
+
+def test_graph_subcycled_replays_match_eager_and_oracle():
+    _need_gpu()
+    wls = _boxes(n=4, seed0=980)
+    eager = GpuRun(wls)
+    graph = GpuRun(wls)
+    oracles = [oracle_run(w) for w in wls]
+    stream = torch.cuda.Stream()
+    dts = [w.dt for w in wls]
+    for rep in range(2):
+        eager.step(2, dts=dts, n_sub=3)
+        with torch.cuda.stream(stream):
+            graph.ctx.step_graph(graph.B, graph.vg, graph.rho, dts, 2, stream, n_sub=3)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for w, o in zip(wls, oracles):
+            o.step(w.B, w.vg, w.rho, w.dt, 2, n_sub=3)
+        De, Dg = eager.deposits(), graph.deposits()
+        pe, pg = eager.particles(), graph.particles()
+        for b, o in enumerate(oracles):
+            assert (Dg[b] == De[b]).all(), f"replay {rep}: box {b} graph != eager"
+            assert (Dg[b] == o.D).all(), f"replay {rep}: box {b} graph != oracle"
+            assert (pg[b][1] == pe[b][1]).all()
+
+
+def test_graph_and_eager_calls_mix_in_one_context():
+    """Eager calls between graph launches may change dt and leave the
+    particle and work-list buffers swapped: the next graph call must see both
+    (it re-uploads the step constants and recaptures)."""
+    _need_gpu()
+    wl = W.gyro2d(nx=24, ny=20, ppc=4, seed=990)
+    g = GpuRun(wl)
+    o = oracle_run(wl)
+    stream = torch.cuda.Stream()
+    dt1, dt2 = wl.dt, 0.7 * wl.dt
+    plan = [("graph", dt1, 2), ("eager", dt2, 1), ("graph", dt1, 2), ("eager", dt1, 3), ("graph", dt1, 2)]
+    for kind, dt, n in plan:
+        if kind == "graph":
+            with torch.cuda.stream(stream):
+                g.ctx.step_graph(g.B, g.vg, g.rho, [dt], n, stream)
+            stream.synchronize()
+            torch.cuda.synchronize()
+        else:
+            g.step(n, dts=[dt])
+        o.step(wl.B, wl.vg, wl.rho, dt, n)
+        (D,) = g.deposits()
+        assert (D == o.D).all(), (kind, dt, n)
+    ((x, v),) = g.particles()
+    assert np.abs(v - o.v).max() <= 1e-12 * np.abs(o.v).max()
