@@ -110,7 +110,10 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
 /* Advances all particles n_steps steps (App. A.2, A.3) through fixed fields.
  * Waits for the stream only when dt differs from the previous call (the new
  * step constants are uploaded).  The call may be captured into a HIP graph if
- * dt equals the previous call's (see also mhdpic_step_graph).
+ * dt equals the previous call's and n_steps is even, so that each replay
+ * leaves the context's buffers as it found them; calls made between replays
+ * of such a graph must keep n_steps even for the same reason (see also
+ * mhdpic_step_graph, which tracks this itself).
  *   B, vg  device, [3][cells] doubles: cell-centred magnetic field and gas velocity
  *   rho    device, [cells] doubles: gas density (read only where hall = 1)
  *   dt     host, [n_boxes] doubles: time step of each box (may be negative)

@@ -811,6 +811,10 @@ int mhdpic_step_sub(mhdpic_ctx* c, const double* B, const double* vg, const doub
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &cap));
     const bool capturing = cap != hipStreamCaptureStatusNone;
+    // a captured call is replayed without this host code: it must leave the
+    // particle, work-list and n, J buffers as it found them
+    if (capturing && n_steps % 2)
+        return fail(MHDPIC_EINVAL, "a captured call needs an even n_steps");
     c->last_stream = s;
     rc = set_dt(c, dt, n_sub, s, capturing);
     if (rc) return rc;

@@ -148,3 +148,29 @@ def test_graph_and_eager_calls_mix_in_one_context():
         assert (D == o.D).all(), (kind, dt, n)
     ((x, v),) = g.particles()
     assert np.abs(v - o.v).max() <= 1e-12 * np.abs(o.v).max()
+
+
+def test_user_captured_step_replays_match_the_oracle():
+    """mhdpic_step captured by the caller (torch.cuda.graph) and replayed,
+    with eager steps and synchronisations between the replays."""
+    _need_gpu()
+    wl = W.gyro2d(nx=20, ny=24, ppc=4, seed=995)
+    g = GpuRun(wl)
+    o = oracle_run(wl)
+    g.step(2)                      # uploads this dt before the capture
+    o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        g.ctx.step(g.B, g.vg, g.rho, [wl.dt], 2, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
+        (D,) = g.deposits()
+        assert (D == o.D).all(), f"replay {rep}"
+        g.step(2)                  # eager work between replays (even n_steps)
+        o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
+        (D,) = g.deposits()
+        assert (D == o.D).all(), f"eager after replay {rep}"
