@@ -154,7 +154,7 @@ int mhdpic_step_sub(mhdpic_ctx* ctx, const double* B, const double* vg, const do
 int mhdpic_feedback(mhdpic_ctx* ctx, const double* B, const double* vg, const double* rho,
                     double* out, void* hip_stream);
 
-/* mhdpic_step through a HIP graph./* mhdpic_step through a HIP graph.  The first call (and any call whose
+/* mhdpic_step through a HIP graph.  The first call (and any call whose
  * B, vg, rho, dt or n_steps differ from the cached ones, or that finds the
  * context's buffers in another state than at capture) captures the n_steps
  * steps into a graph owned by the context; every call then launches that

@@ -47,7 +47,7 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     uint32_t item;
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
-    const BoxDev& bx = boxes[w.box];
+    const BoxDev bx = boxes[w.box];
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     for (int c = threadIdx.x; c < K; c += blockDim.x) s_cnt[c] = 0;

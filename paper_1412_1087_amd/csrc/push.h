@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     if (!item_of_block(a.n_items, item)) return;
     for (int c = threadIdx.x; c < K; c += BLOCK) s_cnt[c] = 0;
     const WorkItem w = a.items[item];
-    const BoxDev& bx = a.boxes[w.box];
+    const BoxDev bx = a.boxes[w.box];  // a copy: kept in registers across the stores
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);
