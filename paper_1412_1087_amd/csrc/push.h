@@ -184,19 +184,26 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         constexpr int ZN = NDIM == 3 ? 3 : 1;
 #pragma unroll 1
         for (int oz2 = 0; oz2 < ZN; ++oz2) {
+            // all 9 x 6 values of the plane first, so the reads overlap
+            R fv[9][6];
+            const R* fp = F + fbase + oz2 * G::PY * G::PX;
+#pragma unroll
+            for (int c9 = 0; c9 < 9; ++c9)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) fv[c9][q] = fp[(c9 / 3) * G::PX + c9 % 3 + q * G::NFF];
 #pragma unroll
             for (int oy2 = 0; oy2 < 3; ++oy2) {
 #pragma unroll
                 for (int ox2 = 0; ox2 < 3; ++ox2) {
                     R wxy = wx[ox2] * wy[oy2];
                     R W = NDIM == 3 ? wxy * wz[oz2] : wxy;
-                    const R* f = F + fbase + (oz2 * G::PY + oy2) * G::PX + ox2;
-                    E[0] = Pol::fma(W, f[0 * G::NFF], E[0]);
-                    E[1] = Pol::fma(W, f[1 * G::NFF], E[1]);
-                    E[2] = Pol::fma(W, f[2 * G::NFF], E[2]);
-                    Bp[0] = Pol::fma(W, f[3 * G::NFF], Bp[0]);
-                    Bp[1] = Pol::fma(W, f[4 * G::NFF], Bp[1]);
-                    Bp[2] = Pol::fma(W, f[5 * G::NFF], Bp[2]);
+                    const R* f = fv[oy2 * 3 + ox2];
+                    E[0] = Pol::fma(W, f[0], E[0]);
+                    E[1] = Pol::fma(W, f[1], E[1]);
+                    E[2] = Pol::fma(W, f[2], E[2]);
+                    Bp[0] = Pol::fma(W, f[3], Bp[0]);
+                    Bp[1] = Pol::fma(W, f[4], Bp[1]);
+                    Bp[2] = Pol::fma(W, f[5], Bp[2]);
                 }
             }
         }
