@@ -264,7 +264,13 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
     cur.stage(st, mm);
     __syncthreads();
     if (nsrc) nxt.load(nsrc, mm);
-    for (int L = threadIdx.x; L < mm.n; L += BLOCK) dst[mm.goff[mm.grp[L]] + (uint32_t)L] = st[mm.from[L]];
+    // a fixed trip count, so the LDS reads of all the thread's slots overlap
+    constexpr int U = kItemParticles / BLOCK;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int L = threadIdx.x + u * BLOCK;
+        if (L < mm.n) dst[mm.goff[mm.grp[L]] + (uint32_t)L] = st[mm.from[L]];
+    }
     __syncthreads();
 }
 
@@ -312,18 +318,27 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     }
     __syncthreads();
     // group bases: the stay classes in class order from the stay group's
-    // offset, the moving groups at their own offsets
-    for (int g = threadIdx.x; g < NG; g += BLOCK) {
-        uint32_t base, lb = 0;
-        for (int q = 0; q < g * RS; ++q) lb += s_n[q];
-        if (g < NCL) {
-            base = off[(size_t)item * K + STAY];
-            for (int q = 0; q < g * RS; ++q) base += s_n[q];
-        } else {
-            base = off[(size_t)item * K + (g - NCL)];
+    // offset, the moving groups at their own offsets; lane g of the first
+    // wave scans the group sizes
+    static_assert(NG <= 64, "one lane per group");
+    if (threadIdx.x < 64) {
+        const int g = threadIdx.x;
+        uint32_t t = 0;
+        if (g < NG)
+#pragma unroll
+            for (int b = 0; b < RS; ++b) t += s_n[g * RS + b];
+        uint32_t x = t;  // inclusive scan over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (g >= o) x += y;
         }
-        s_off[g] = base - lb;  // destination of local slot L of group g: s_off[g] + L
-        s_lbase[g] = lb;
+        const uint32_t lb = x - t;  // slots of the groups before g
+        if (g < NG) {
+            const uint32_t base = g < NCL ? off[(size_t)item * K + STAY] + lb
+                                          : off[(size_t)item * K + (g - NCL)];
+            s_off[g] = base - lb;  // destination of local slot L of group g: s_off[g] + L
+            s_lbase[g] = lb;
+        }
     }
     __syncthreads();
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
