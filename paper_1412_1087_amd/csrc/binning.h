@@ -307,14 +307,50 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
     if (w.end - w.begin > kItemParticles) return;  // never built larger
+    using R = typename PS::R;
+    constexpr int NR = NDIM + 5;  // offsets, four-velocity, m, q/m
+    constexpr int U = kItemParticles / BLOCK;
+    const MoveMap mm{s_src, s_grp, s_off, w.begin, w.end - w.begin};
+    const R* rsrc[NR];
+    R* rdst[NR];
+#pragma unroll
+    for (int q = 0; q < NDIM; ++q) {
+        rsrc[q] = A.d[q];
+        rdst[q] = Bo.d[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        rsrc[NDIM + q] = A.v[q];
+        rdst[NDIM + q] = Bo.v[q];
+    }
+    rsrc[NDIM + 3] = A.m;
+    rdst[NDIM + 3] = Bo.m;
+    rsrc[NDIM + 4] = A.qm;
+    rdst[NDIM + 4] = Bo.qm;
+    // the codes, the cells and the first array are loaded before the ranking
+    // so that their latency overlaps it
+    uint32_t cr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int L = threadIdx.x + u * BLOCK;
+        cr[u] = L < mm.n ? code[w.begin + L] : 0u;
+    }
+    ItemRegs<BLOCK, uint32_t> rcell;
+    ItemRegs<BLOCK, int32_t> rpid;
+    ItemRegs<BLOCK, R> rbuf[2];
+    rcell.load(A.cell, mm);
+    rbuf[0].load(rsrc[0], mm);
     for (int c = threadIdx.x; c < NG * RS; c += BLOCK) s_n[c] = 0;
     __syncthreads();
-    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
-        const uint32_t cr = code[j];
-        const int k = code_dir(cr), b = code_residue(cr);
-        const int g = k == STAY ? code_class(cr) : NCL + k;
-        const uint32_t r = atomicAdd(&s_n[g * RS + b], 1u);
-        s_key[j - w.begin] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int L = threadIdx.x + u * BLOCK;
+        if (L < mm.n) {
+            const int k = code_dir(cr[u]), b = code_residue(cr[u]);
+            const int g = k == STAY ? code_class(cr[u]) : NCL + k;
+            const uint32_t r = atomicAdd(&s_n[g * RS + b], 1u);
+            s_key[L] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16);
+        }
     }
     __syncthreads();
     // group bases: the stay classes in class order from the stay group's
@@ -356,35 +392,14 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         s_grp[s_lbase[g] + pos] = (uint8_t)g;
     }
     __syncthreads();
-    // the arrays one after another, through LDS, in destination order
-    using R = typename PS::R;
-    constexpr int NR = NDIM + 5;  // offsets, four-velocity, m, q/m
-    const MoveMap mm{s_src, s_grp, s_off, w.begin, w.end - w.begin};
-    const R* rsrc[NR];
-    R* rdst[NR];
+    // the arrays one after another, through LDS, in destination order, with
+    // two arrays in flight: array q+2 is loaded while array q is stored
+    move_step<BLOCK>(rcell, Bo.cell, s_stage, rbuf[1], rsrc[1], mm);
 #pragma unroll
-    for (int q = 0; q < NDIM; ++q) {
-        rsrc[q] = A.d[q];
-        rdst[q] = Bo.d[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        rsrc[NDIM + q] = A.v[q];
-        rdst[NDIM + q] = Bo.v[q];
-    }
-    rsrc[NDIM + 3] = A.m;
-    rdst[NDIM + 3] = Bo.m;
-    rsrc[NDIM + 4] = A.qm;
-    rdst[NDIM + 4] = Bo.qm;
-    ItemRegs<BLOCK, uint32_t> rcell;
-    ItemRegs<BLOCK, int32_t> rpid;
-    ItemRegs<BLOCK, R> rbuf[2];
-    rcell.load(A.cell, mm);
-    move_step<BLOCK>(rcell, Bo.cell, s_stage, rbuf[0], rsrc[0], mm);
-#pragma unroll
-    for (int q = 0; q + 1 < NR; ++q)
-        move_step<BLOCK>(rbuf[q & 1], rdst[q], s_stage, rbuf[(q + 1) & 1], rsrc[q + 1], mm);
-    move_step<BLOCK>(rbuf[(NR - 1) & 1], rdst[NR - 1], s_stage, rpid, A.pid, mm);
+    for (int q = 0; q + 2 < NR; ++q)
+        move_step<BLOCK>(rbuf[q & 1], rdst[q], s_stage, rbuf[q & 1], rsrc[q + 2], mm);
+    move_step<BLOCK>(rbuf[(NR - 2) & 1], rdst[NR - 2], s_stage, rpid, A.pid, mm);
+    move_step<BLOCK>(rbuf[(NR - 1) & 1], rdst[NR - 1], s_stage, rcell, (const uint32_t*)nullptr, mm);
     move_step<BLOCK>(rpid, Bo.pid, s_stage, rcell, (const uint32_t*)nullptr, mm);
 }
 
