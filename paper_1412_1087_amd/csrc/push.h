@@ -274,7 +274,11 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         const int p0 = Pol::drift(e0, k1.u[0], hx), p1 = Pol::drift(e1, k1.u[1], hy);
         const int p2 = NDIM == 3 ? Pol::drift(e2, k1.u[2], hz) : 0;
         a.code[j] = pack_code(k, bank_residue<NDIM>(bx, T, tx, ty, tz, k, ni), shift_class<NDIM>(p0, p1, p2));
-        atomicAdd(&s_cnt[k], 1u);
+        // most particles stay in the tile: one LDS atomic per wave for them
+        const uint64_t stays = __ballot(k == Codes<NDIM>::STAY);
+        if (k != Codes<NDIM>::STAY) atomicAdd(&s_cnt[k], 1u);
+        else if (lane_id() == __ffsll((unsigned long long)stays) - 1)
+            atomicAdd(&s_cnt[k], (uint32_t)__popcll(stays));
     }
     if (errbits) latch(a.err, errbits);
     __syncthreads();
