@@ -422,4 +422,83 @@ __global__ void k_key_cell(PS P, uint32_t* __restrict__ key, uint32_t* __restric
     wave_claim(count, k, act);
 }
 
+// Initial sort with per-block tile histograms in LDS, for a tile count that
+// fits (NT <= kSortLdsTiles): each block takes kSortChunk consecutive
+// particles, counts their tiles in LDS and adds each non-zero count to the
+// global counter once, so a counter sees one atomic per block however the
+// particles are ordered.
+constexpr int kSortChunk = 4096;
+constexpr int kSortLdsTiles = 8192;
+
+template <int NDIM, typename PS>
+__global__ void __launch_bounds__(256)
+k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
+                const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off, int nb,
+                int64_t N, int3 T, int NT) {
+    extern __shared__ uint32_t s_h[];
+    constexpr int U = kSortChunk / 256;
+    for (int t = threadIdx.x; t < NT; t += 256) s_h[t] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * kSortChunk;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + threadIdx.x + u * 256;
+        if (j < N) {
+            const BoxDev& bx = boxes[find_box(part_off, nb, j)];
+            int i[3];
+            unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+            const uint32_t k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+            key[j] = k;
+            atomicAdd(&s_h[k], 1u);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NT; t += 256)
+        if (s_h[t]) atomicAdd(&count[t], s_h[t]);
+}
+
+// Moves every particle to its slot in the tile-sorted order: the same chunks
+// and LDS histograms as k_key_count_lds; each block claims one range per
+// tile from the global cursor and hands out its slots in LDS.
+template <int NDIM, typename PS>
+__global__ void __launch_bounds__(256)
+k_scatter_lds(PS A, PS Bo, const uint32_t* __restrict__ key, uint32_t* __restrict__ cursor,
+              int64_t N, int NT) {
+    extern __shared__ uint32_t s_h[];
+    constexpr int U = kSortChunk / 256;
+    for (int t = threadIdx.x; t < NT; t += 256) s_h[t] = 0;
+    __syncthreads();
+    const int64_t j0 = (int64_t)blockIdx.x * kSortChunk;
+    uint32_t k[U], r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + threadIdx.x + u * 256;
+        k[u] = j < N ? key[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + threadIdx.x + u * 256;
+        r[u] = j < N ? atomicAdd(&s_h[k[u]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NT; t += 256) {
+        const uint32_t c = s_h[t];
+        if (c) s_h[t] = atomicAdd(&cursor[t], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = j0 + threadIdx.x + u * 256;
+        if (j < N) {
+            const uint32_t sl = s_h[k[u]] + r[u];
+            Bo.cell[sl] = A.cell[j];
+            for (int d = 0; d < NDIM; ++d) Bo.d[d][sl] = A.d[d][j];
+            for (int d = 0; d < 3; ++d) Bo.v[d][sl] = A.v[d][j];
+            Bo.m[sl] = A.m[j];
+            Bo.qm[sl] = A.qm[j];
+            Bo.pid[sl] = A.pid[j];
+        }
+    }
+}
+
 }  // namespace mhdpic

@@ -362,7 +362,16 @@ int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
     PS A = part<PS, T>(c, 0);
     PS Bo = part<PS, T>(c, 1);
     fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
-    if (L.N > 0)
+    // per-block LDS histograms when the tiles fit, else one atomic per
+    // distinct tile in each wave
+    const bool lds = L.NT <= kSortLdsTiles;
+    const unsigned gC = (unsigned)((L.N + kSortChunk - 1) / kSortChunk);
+    const size_t hbytes = (size_t)L.NT * sizeof(uint32_t);
+    if (L.N > 0 && lds)
+        hipLaunchKernelGGL((k_key_count_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
+                           at<int64_t>(c, L.part_off), c->nb, L.N, T3, L.NT);
+    else if (L.N > 0)
         hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
                            at<int64_t>(c, L.part_off), c->nb, L.N, T3);
@@ -370,7 +379,10 @@ int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
                        at<uint32_t>(c, L.start), at<uint32_t>(c, L.cursor), at<int32_t>(c, L.tile_box),
                        at<WorkItem>(c, L.items[0]), at<uint32_t>(c, L.item_first[0]),
                        at<uint32_t>(c, L.n_items[0]), L.NT, kItemParticles);
-    if (L.N > 0)
+    if (L.N > 0 && lds)
+        hipLaunchKernelGGL((k_scatter_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A, Bo,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N, L.NT);
+    else if (L.N > 0)
         hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A, Bo,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N);
     c->cur = 1;

@@ -112,6 +112,12 @@ def test_parity_3d_tiles(tile):
     _parity(W.bell3d(n=(11, 10, 9), ppc=2, seed=11), n_steps=1, tile=tile)
 
 
+def test_parity_many_tiles_initial_sort_fallback():
+    # 256 x 33 tiles of 16 x 16 cells: more tiles than the initial sort's LDS
+    # histograms hold, so it counts with per-wave global atomics instead
+    _parity(W.shock2d(nx=4096, ny=528, n_particles=100_000, seed=14), n_steps=1)
+
+
 def test_parity_tiny_boxes_wrap_onto_themselves():
     # boxes smaller than a tile and its ghost layers
     _parity(W.gyro2d(nx=3, ny=2, ppc=7, seed=12), n_steps=3)
