@@ -79,7 +79,7 @@ bool tile_supported(int ndim, int prec, const TileShape& t) {
 
 TileShape default_tile(int ndim, int prec) {
     (void)prec;
-    if (ndim == 2) return {16, 16, 1};
+    if (ndim == 2) return {32, 16, 1};
     return {8, 4, 4};
 }
 

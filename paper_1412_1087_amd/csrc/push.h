@@ -102,6 +102,26 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
     for (int c = 0; c < 4; ++c) atomicAdd(pc + c * NB, (unsigned long long)(tot[c] - acc[c]));
 }
 
+// One particle's stored state (in 2D the third offset reads as 0).
+template <int NDIM, typename R>
+struct PartRec {
+    uint32_t cell = 0;
+    R d[3] = {R(0), R(0), R(0)}, v[3] = {R(0), R(0), R(0)};
+    R m = R(0), qm = R(0);
+    template <typename PS>
+    __device__ __forceinline__ void load(const PS& P, int j) {
+        cell = P.cell[j];
+        d[0] = P.d[0][j];
+        d[1] = P.d[1][j];
+        d[2] = NDIM == 3 ? P.d[2][j] : R(0);
+        v[0] = P.v[0][j];
+        v[1] = P.v[1][j];
+        v[2] = P.v[2][j];
+        m = P.m[j];
+        qm = P.qm[j];
+    }
+};
+
 template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
@@ -149,12 +169,24 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     const int3 T = make_int3(TX, TY, TZ);
     uint32_t errbits = 0;
 
+    // In 3D the LDS limits a CU to two waves per SIMD, so registers are free
+    // to load the next particle while this one is pushed; in 2D they are not.
+    constexpr bool kPrefetch = NDIM == 3;
+    PartRec<NDIM, R> nxt;
+    if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.P, w.begin + (int)threadIdx.x);
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        PartRec<NDIM, R> cur;
+        if (kPrefetch) {
+            cur = nxt;
+            if (j + BLOCK < w.end) nxt.load(a.P, j + BLOCK);
+        } else {
+            cur.load(a.P, j);
+        }
         int i[3];
-        unpack_cell<NDIM>(a.P.cell[j], i[0], i[1], i[2]);
-        R dl[3] = {a.P.d[0][j], a.P.d[1][j], NDIM == 3 ? a.P.d[2][j] : R(0)};
-        R v[3] = {a.P.v[0][j], a.P.v[1][j], a.P.v[2][j]};
-        const double m = (double)a.P.m[j], qm = (double)a.P.qm[j];
+        unpack_cell<NDIM>(cur.cell, i[0], i[1], i[2]);
+        R dl[3] = {cur.d[0], cur.d[1], cur.d[2]};
+        R v[3] = {cur.v[0], cur.v[1], cur.v[2]};
+        const double m = (double)cur.m, qm = (double)cur.qm;
 
         typename Pol::K k0 = Pol::kin(v, C, C2, iC);
         // drift to x^(n+1/2)

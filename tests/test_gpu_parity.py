@@ -102,7 +102,7 @@ def test_parity_shock2d_small():
     _parity(W.shock2d(nx=512, ny=32, n_particles=512 * 32 * 8, seed=9), n_steps=2)
 
 
-@pytest.mark.parametrize("tile", [(8, 8, 1), (32, 16, 1), (64, 16, 1)])
+@pytest.mark.parametrize("tile", [(8, 8, 1), (16, 16, 1), (32, 32, 1), (64, 16, 1)])
 def test_parity_2d_tiles(tile):
     _parity(W.gyro2d(nx=37, ny=23, ppc=5, seed=10), n_steps=2, tile=tile)
 
@@ -115,7 +115,7 @@ def test_parity_3d_tiles(tile):
 def test_parity_many_tiles_initial_sort_fallback():
     # 256 x 33 tiles of 16 x 16 cells: more tiles than the initial sort's LDS
     # histograms hold, so it counts with per-wave global atomics instead
-    _parity(W.shock2d(nx=4096, ny=528, n_particles=100_000, seed=14), n_steps=1)
+    _parity(W.shock2d(nx=4096, ny=528, n_particles=100_000, seed=14), n_steps=1, tile=(16, 16, 1))
 
 
 def test_parity_tiny_boxes_wrap_onto_themselves():

@@ -41,7 +41,7 @@ def _compare(wl, g, o, tag):
 @pytest.mark.parametrize("n_sub", [2, 5])
 def test_subcycled_2d_matches_oracle(n_sub):
     _need_gpu()
-    wl = W.gyro2d(nx=40, ny=36, ppc=6, seed=1200 + n_sub)   # tiles of 16x16 plus ragged edges
+    wl = W.gyro2d(nx=40, ny=36, ppc=6, seed=1200 + n_sub)   # tiles of 32x16 plus ragged edges
     g = GpuRun(wl)
     o = oracle_run(wl)
     for rep in range(2):
