@@ -211,13 +211,18 @@ int mhdpic_destroy(mhdpic_ctx* ctx);
 const char* mhdpic_last_error(void);
 
 /* Per-phase kernel timing with HIP events recorded on the launch stream.
- * mhdpic_timing_enable(ctx, 1) starts recording an event pair around every
- * later phase launch of mhdpic_step; (ctx, 0) stops.  mhdpic_timing_read waits
- * for the recorded events, writes the summed milliseconds and the number of
- * launches of each phase (ms[4], launches[4]: 0 = binning (rekey, scan,
- * scatter), 1 = cell-centred field preparation, 2 = fused gather/push/deposit,
- * 3 = buffer clears) and clears the record. */
-int mhdpic_timing_enable(mhdpic_ctx* ctx, int32_t enable);
+ * Phases: 0 = binning (rekey, scan, scatter), 1 = cell-centred field
+ * preparation, 2 = fused gather/push/deposit, 3 = buffer clears.
+ * mhdpic_timing_enable(ctx, phases) starts recording an event pair around
+ * every later launch of the phases whose bit (1 << phase) is set in phases
+ * (MHDPIC_TIMING_ALL: all four); 0 stops; other values are EINVAL.  Each
+ * recorded event costs some microseconds of stream time, so time only the
+ * phases you need.  Launches inside a graph capture are never timed.
+ * mhdpic_timing_read waits for the recorded events, writes the summed
+ * milliseconds and the number of timed launches of each phase (ms[4],
+ * launches[4]) and clears the record. */
+#define MHDPIC_TIMING_ALL 15
+int mhdpic_timing_enable(mhdpic_ctx* ctx, int32_t phases);
 int mhdpic_timing_read(mhdpic_ctx* ctx, double* ms, int64_t* launches);
 
 /* Arithmetic self-test: out[0][i] = sqrt(a[i]), out[1][i] = a[i]/b[i],

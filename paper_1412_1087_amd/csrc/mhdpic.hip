@@ -130,8 +130,8 @@ struct mhdpic_ctx {
     uint32_t* err_host = nullptr;  // pinned copy of the error word
     hipEvent_t err_event = nullptr;
     bool err_pending = false;
-    // optional per-phase timing
-    bool timing = false;
+    // optional per-phase timing: bit k set times phase k
+    uint32_t timing = 0;
     struct Mark {
         int phase;
         hipEvent_t a, b;
@@ -523,13 +523,13 @@ struct PhaseTimer {
         return e;
     }
     PhaseTimer(mhdpic_ctx* c_, hipStream_t s_, int phase_) : c(c_), s(s_), phase(phase_) {
-        if (!c->timing) return;
+        if (!((c->timing >> phase) & 1u)) return;
         a = take();
         b = take();
         if (a && b) (void)hipEventRecord(a, s);
     }
     ~PhaseTimer() {
-        if (!c->timing || !a || !b) return;
+        if (!((c->timing >> phase) & 1u) || !a || !b) return;
         (void)hipEventRecord(b, s);
         c->marks.push_back({phase, a, b});
     }
@@ -605,8 +605,8 @@ int set_dt(mhdpic_ctx* c, const double* dt, int32_t n_sub, hipStream_t s, bool c
 int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
                   int32_t n_steps, int32_t n_sub, hipStream_t s, bool allow_timing) {
     if (!rho) rho = B;  // never read without the Hall term
-    const bool saved = c->timing;
-    c->timing = c->timing && allow_timing;
+    const uint32_t saved = c->timing;
+    if (!allow_timing) c->timing = 0;
     int rc;
     {
         PhaseTimer t(c, s, 0);
@@ -1033,9 +1033,10 @@ int mhdpic_check(mhdpic_ctx* c, void* hip_stream) {
     return MHDPIC_OK;
 }
 
-int mhdpic_timing_enable(mhdpic_ctx* c, int32_t enable) {
+int mhdpic_timing_enable(mhdpic_ctx* c, int32_t phases) {
     if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
-    c->timing = enable != 0;
+    if (phases < 0 || phases > MHDPIC_TIMING_ALL) return fail(MHDPIC_EINVAL, "phases must be a mask of bits 0..3");
+    c->timing = (uint32_t)phases;
     return MHDPIC_OK;
 }
 

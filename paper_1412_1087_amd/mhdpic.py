@@ -246,10 +246,17 @@ class Context:
         _check(lib().mhdpic_particles_read(self._h, _ptr(x), _ptr(v), _stream(stream)))
         return x, v
 
-    def timing(self, enable: bool):
-        _check(lib().mhdpic_timing_enable(self._h, int(bool(enable))))
-
     PHASES = ("bin", "fieldprep", "push", "clear")
+
+    def timing(self, enable: bool, phases=None):
+        """Event timing of the named phases (all four if None) from now on;
+        timing(False) stops."""
+        mask = 0
+        if enable:
+            names = self.PHASES if phases is None else phases
+            for p in names:
+                mask |= 1 << self.PHASES.index(p)
+        _check(lib().mhdpic_timing_enable(self._h, mask))
 
     def timing_read(self) -> dict:
         ms = (ct.c_double * 4)()
