@@ -118,6 +118,27 @@ def test_parity_many_tiles_initial_sort_fallback():
     _parity(W.shock2d(nx=4096, ny=528, n_particles=100_000, seed=14), n_steps=1, tile=(16, 16, 1))
 
 
+@pytest.mark.parametrize("order", ["sorted", "reversed", "one_tile_first"])
+def test_parity_input_order(order):
+    # the initial sort sees long runs of one tile (sorted input), runs in
+    # descending tile order, or one tile's particles packed into few blocks
+    import dataclasses
+    wl = W.bell3d(n=(24, 16, 12), ppc=6, seed=15)
+    box = wl.box
+    cell = [np.floor(wl.x[d] / box.dx[d]).astype(np.int64) for d in range(3)]
+    key = (cell[2] * box.n[1] + cell[1]) * box.n[0] + cell[0]
+    if order == "sorted":
+        perm = np.argsort(key, kind="stable")
+    elif order == "reversed":
+        perm = np.argsort(-key, kind="stable")
+    else:
+        first = (cell[0] < 8) & (cell[1] < 4) & (cell[2] < 4)
+        perm = np.r_[np.flatnonzero(first), np.flatnonzero(~first)]
+    wl = dataclasses.replace(wl, x=np.ascontiguousarray(wl.x[:, perm]), v=np.ascontiguousarray(wl.v[:, perm]),
+                             m=wl.m[perm].copy(), qm=wl.qm[perm].copy())
+    _parity(wl, n_steps=2)
+
+
 def test_parity_tiny_boxes_wrap_onto_themselves():
     # boxes smaller than a tile and its ghost layers
     _parity(W.gyro2d(nx=3, ny=2, ppc=7, seed=12), n_steps=3)
