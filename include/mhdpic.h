@@ -212,7 +212,9 @@ const char* mhdpic_last_error(void);
 
 /* Per-phase kernel timing with HIP events recorded on the launch stream.
  * Phases: 0 = binning (rekey, scan, scatter), 1 = cell-centred field
- * preparation, 2 = fused gather/push/deposit, 3 = buffer clears.
+ * preparation (which also clears the next n_CR, J_CR buffer), 2 = fused
+ * gather/push/deposit, 3 = separate buffer clears (the step has none now;
+ * the slot is kept so that the arrays keep their size).
  * mhdpic_timing_enable(ctx, phases) starts recording an event pair around
  * every later launch of the phases whose bit (1 << phase) is set in phases
  * (MHDPIC_TIMING_ALL: all four); 0 stops; other values are EINVAL.  Each

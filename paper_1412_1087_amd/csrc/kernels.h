@@ -317,11 +317,13 @@ __device__ __forceinline__ bool item_of_block(const uint32_t* n_items, uint32_t&
 // cell-centred fields: E0 = -v_g x B and the CR-Hall correction (Sec. 2.1)
 // ---------------------------------------------------------------------------
 
-// Writes EB[cell] = (Ex, Ey, Ez, Bx, By, Bz) interleaved for the gather.
+// Writes EB[cell] = (Ex, Ey, Ez, Bx, By, Bz) interleaved for the gather, and
+// clears the cell's n_CR, J_CR in nJ_next, which the push then fills.
 template <typename TF>
 __global__ void k_fieldprep(TF* __restrict__ EB, const double* __restrict__ B,
                             const double* __restrict__ vg, const double* __restrict__ rho,
-                            const int64_t* __restrict__ nJ, const BoxDev* __restrict__ boxes,
+                            const int64_t* __restrict__ nJ, int64_t* __restrict__ nJ_next,
+                            const BoxDev* __restrict__ boxes,
                             const int64_t* __restrict__ cell_off, int nb, int64_t NC) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= NC) return;
@@ -356,6 +358,8 @@ __global__ void k_fieldprep(TF* __restrict__ EB, const double* __restrict__ B,
     o[3] = (TF)b0;
     o[4] = (TF)b1;
     o[5] = (TF)b2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nJ_next[q * NC + c] = 0;
 }
 
 // Cell-centred feedback of the predictor step (App. A.3), in code units

@@ -401,8 +401,10 @@ int launch_initial_sort_any(mhdpic_ctx* c, hipStream_t s) {
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
 int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
-    // 2D: two blocks of eight waves fill a CU (four waves per SIMD) within the LDS
-    constexpr int BLOCK = NDIM == 2 ? 512 : 256;
+    // Two blocks of eight waves (four per SIMD) where the kernel fits in 128
+    // VGPRs: 2D, and 3D in binary32.  The binary64 3D kernel needs more
+    // registers, and its 70 KB of LDS allow two blocks of four waves.
+    constexpr int BLOCK = (NDIM == 2 || std::is_same<typename Pol::R, float>::value) ? 512 : 256;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     const Layout& L = c->L;
@@ -495,13 +497,14 @@ int launch_fieldprep(mhdpic_ctx* c, const double* B, const double* vg, const dou
                      hipStream_t s) {
     const Layout& L = c->L;
     const int64_t* nJcur = at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1);
+    int64_t* nJnext = at<int64_t>(c, c->nj == 0 ? L.nJ1 : L.nJ0);
     if (c->precision == MHDPIC_FP64)
         hipLaunchKernelGGL(k_fieldprep<double>, dim3(grid_for(L.NC, 256)), dim3(256), 0, s,
-                           at<double>(c, L.EB), B, vg, rho, nJcur, at<BoxDev>(c, L.boxes),
+                           at<double>(c, L.EB), B, vg, rho, nJcur, nJnext, at<BoxDev>(c, L.boxes),
                            at<int64_t>(c, L.cell_off), c->nb, L.NC);
     else
         hipLaunchKernelGGL(k_fieldprep<float>, dim3(grid_for(L.NC, 256)), dim3(256), 0, s,
-                           at<float>(c, L.EB), B, vg, rho, nJcur, at<BoxDev>(c, L.boxes),
+                           at<float>(c, L.EB), B, vg, rho, nJcur, nJnext, at<BoxDev>(c, L.boxes),
                            at<int64_t>(c, L.cell_off), c->nb, L.NC);
     return MHDPIC_OK;
 }
@@ -614,15 +617,10 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
     }
     for (int st = 0; st < n_steps && !rc; ++st) {
         {
-            PhaseTimer t(c, s, 1);
+            PhaseTimer t(c, s, 1);  // also clears the next n_CR, J_CR buffer
             rc = launch_fieldprep(c, B, vg, rho, s);
         }
         if (rc) break;
-        {
-            PhaseTimer t(c, s, 3);
-            int64_t* next = at<int64_t>(c, c->nj == 0 ? c->L.nJ1 : c->L.nJ0);
-            fill_i64(next, 4 * c->L.NC, s);
-        }
         for (int sub = 0; sub < n_sub && !rc; ++sub) {
             const bool last_sub = sub + 1 == n_sub;
             {

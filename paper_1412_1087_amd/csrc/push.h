@@ -169,8 +169,10 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     const int3 T = make_int3(TX, TY, TZ);
     uint32_t errbits = 0;
 
-    // In 3D the LDS limits a CU to two waves per SIMD, so registers are free
-    // to load the next particle while this one is pushed; in 2D they are not.
+    // In 3D the next particle is loaded while this one is pushed: binary64
+    // runs two waves per SIMD (LDS-limited), so registers are free, and the
+    // binary32 kernel still fits the 128 registers of four waves per SIMD.
+    // In 2D the registers are not there.
     constexpr bool kPrefetch = NDIM == 3;
     PartRec<NDIM, R> nxt;
     if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.P, w.begin + (int)threadIdx.x);
