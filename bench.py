@@ -240,6 +240,29 @@ def run_strip_form(steps: int, warmup: int):
 FEEDBACK_BYTES_PER_CELL = 168  # read n_CR, J_CR (32), B, v_g (48), rho (8); write 10 doubles
 
 
+def measure_copy_gbps(nbytes: int = 1 << 31, reps: int = 5):
+    """Device-to-device copy bandwidth (bytes read + written per second), the
+    median of reps copies of nbytes: the HBM rate a streaming kernel reaches
+    on this GPU, beside the published 8 TB/s peak."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    t = sorted(times)[len(times) // 2]
+    return round(2 * nbytes / t / 1e9, 1)
+
+
 def time_feedback(ctx, B, vg, rho, n_cells: int, reps: int = 20):
     """Average launch time of the cell-centred feedback kernel and its share
     of the HBM peak at 168 algorithmic bytes per cell."""
@@ -445,6 +468,8 @@ def main():
         forms["subcycled"] = run_subcycled_form(20, 2)
         torch.cuda.empty_cache()
         forms["strip2d"] = run_strip_form(20, 3)
+    copy_gbps = measure_copy_gbps()
+    log(f"device copy: {copy_gbps} GB/s (read + written)")
     cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     phases = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in g["phases"].items()}
     phases["steps"] = g["breakdown_steps"]
@@ -471,6 +496,7 @@ def main():
         "forms": forms,
         "hbm_frac_whole_step": round(
             (alg["per_launch"] / (ms * 1e-3 / args.steps)) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_GBps_measured": copy_gbps,
         "checksum": g["checksum"],
         "kernel_hash": kernel_hash(),
     }
