@@ -428,7 +428,7 @@ __global__ void k_key_cell(PS P, uint32_t* __restrict__ key, uint32_t* __restric
 // global counter once, so a counter sees one atomic per block however the
 // particles are ordered.
 constexpr int kSortChunk = 4096;
-constexpr int kSortLdsTiles = 8192;
+constexpr int kSortLdsTiles = 32768;  // 128 KB of LDS histogram at most
 
 template <int NDIM, typename PS>
 __global__ void __launch_bounds__(256)

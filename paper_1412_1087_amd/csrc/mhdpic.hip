@@ -362,11 +362,17 @@ int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
     PS A = part<PS, T>(c, 0);
     PS Bo = part<PS, T>(c, 1);
     fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
-    // per-block LDS histograms when the tiles fit, else one atomic per
-    // distinct tile in each wave
+    // per-block LDS histograms when the tiles fit (up to 128 KB of LDS), else
+    // one atomic per distinct tile in each wave
     const bool lds = L.NT <= kSortLdsTiles;
     const unsigned gC = (unsigned)((L.N + kSortChunk - 1) / kSortChunk);
     const size_t hbytes = (size_t)L.NT * sizeof(uint32_t);
+    if (lds && hbytes > 65536) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_key_count_lds<NDIM, PS>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)hbytes));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_scatter_lds<NDIM, PS>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)hbytes));
+    }
     if (L.N > 0 && lds)
         hipLaunchKernelGGL((k_key_count_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),

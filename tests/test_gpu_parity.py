@@ -112,10 +112,15 @@ def test_parity_3d_tiles(tile):
     _parity(W.bell3d(n=(11, 10, 9), ppc=2, seed=11), n_steps=1, tile=tile)
 
 
-def test_parity_many_tiles_initial_sort_fallback():
-    # 256 x 33 tiles of 16 x 16 cells: more tiles than the initial sort's LDS
-    # histograms hold, so it counts with per-wave global atomics instead
+def test_parity_many_tiles_initial_sort_large_histogram():
+    # 256 x 33 tiles of 16 x 16 cells: an LDS histogram of more than 32 KB
     _parity(W.shock2d(nx=4096, ny=528, n_particles=100_000, seed=14), n_steps=1, tile=(16, 16, 1))
+
+
+def test_parity_many_tiles_initial_sort_fallback():
+    # 512 x 65 tiles of 8 x 8 cells: more tiles than the initial sort's LDS
+    # histograms hold (32768), so it counts with per-wave global atomics
+    _parity(W.shock2d(nx=4096, ny=520, n_particles=100_000, seed=16), n_steps=1, tile=(8, 8, 1))
 
 
 @pytest.mark.parametrize("order", ["sorted", "reversed", "one_tile_first"])
