@@ -468,7 +468,8 @@ def main():
         forms["subcycled"] = run_subcycled_form(20, 2)
         torch.cuda.empty_cache()
         forms["strip2d"] = run_strip_form(20, 3)
-    copy_gbps = measure_copy_gbps()
+    # (a counter-collection run keeps its one calibration copy alone)
+    copy_gbps = None if args.calibrate_copy else measure_copy_gbps()
     log(f"device copy: {copy_gbps} GB/s (read + written)")
     cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     phases = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in g["phases"].items()}
