@@ -56,8 +56,9 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
         int i[3], cls;
         half_step_cell<Pol, NDIM>(P, j, bx, i, cls);
-        int k = move_code<NDIM>(bx, T, tx, ty, tz, i, errbits);
-        code[j] = pack_code(k, bank_residue<NDIM>(bx, T, tx, ty, tz, k, i), cls);
+        int res;
+        const int k = move_code<NDIM>(bx, T, tx, ty, tz, i, errbits, res);
+        code[j] = pack_code(k, res, cls);
         atomicAdd(&s_cnt[k], 1u);
     }
     if (errbits) latch(err, errbits);

@@ -233,11 +233,8 @@ struct Codes {
 // tiles: 1 = same, 2 = next, 0 = previous; -1 if farther.
 __device__ __forceinline__ int dir_code(int a, int b, int n) {
     int d = b - a;
-    if (d < 0) d += n;
-    if (d == 0) return 1;
-    if (d == 1) return 2;
-    if (d == n - 1) return 0;
-    return -1;
+    d += d < 0 ? n : 0;
+    return d == 0 ? 1 : (d == 1 ? 2 : (d == n - 1 ? 0 : -1));  // selects, no branches
 }
 
 template <int NDIM>
@@ -248,43 +245,41 @@ __device__ __forceinline__ void tile_coords(const BoxDev& bx, int tile, int& tx,
     tz = NDIM == 3 ? lt / (bx.nt[0] * bx.nt[1]) : 0;
 }
 
-// Code of the move from the item's tile (tx,ty,tz) to the tile holding cell i;
-// Codes::STAY (and an error bit) if the cell is farther than one tile.
-template <int NDIM>
-__device__ __forceinline__ int move_code(const BoxDev& bx, int3 T, int tx, int ty, int tz,
-                                         const int i[3], uint32_t& errbits) {
-    int cx = dir_code(tx, tile_index(bx, 0, i[0], T.x), bx.nt[0]);
-    int cy = dir_code(ty, tile_index(bx, 1, i[1], T.y), bx.nt[1]);
-    int cz = NDIM == 3 ? dir_code(tz, tile_index(bx, 2, i[2], T.z), bx.nt[2]) : 0;
-    if (cx < 0 || cy < 0 || cz < 0) {
-        errbits |= ERRBIT_STATE;
-        return Codes<NDIM>::STAY;
-    }
-    return NDIM == 3 ? (cz * 3 + cy) * 3 + cx : cy * 3 + cx;
-}
-
-// Bank residue of the cell ni in the LDS geometry of the destination tile of
-// code k (strides T.x + 4, T.y + 4, ghost width 2).  64-bit words of equal
-// residue share a bank pair; the binning orders particles so that 16
-// consecutive lanes have distinct residues.
+// Bank residues: 64-bit LDS words of equal residue (index mod kResidues)
+// share a bank pair; the binning orders particles so that 16 consecutive
+// lanes have distinct residues.
 #ifndef MHDPIC_RESIDUES
 #define MHDPIC_RESIDUES 16
 #endif
 constexpr int kResidues = MHDPIC_RESIDUES;
 
-__device__ __forceinline__ int ring(int t, int n) { return t < 0 ? t + n : (t >= n ? t - n : t); }
-
+// Code of the move from the item's tile (tx,ty,tz) to the tile holding cell i
+// (Codes::STAY and an error bit if that tile is farther than one tile away),
+// and in `residue` the bank residue of cell i in the LDS geometry of the
+// destination tile (strides T.x + 4, T.y + 4, ghost width 2; the item's own
+// tile after an error).
 template <int NDIM>
-__device__ __forceinline__ int bank_residue(const BoxDev& bx, int3 T, int tx, int ty, int tz, int k,
-                                            const int ni[3]) {
-    int dx = ring(tx + k % 3 - 1, bx.nt[0]);
-    int dy = ring(ty + (k / 3) % 3 - 1, bx.nt[1]);
-    int dz = NDIM == 3 ? ring(tz + k / 9 - 1, bx.nt[2]) : 0;
-    int lx = ni[0] - tile_origin(bx, 0, dx, T.x) + 2;
-    int ly = ni[1] - tile_origin(bx, 1, dy, T.y) + 2;
+__device__ __forceinline__ int move_code(const BoxDev& bx, int3 T, int tx, int ty, int tz,
+                                         const int i[3], uint32_t& errbits, int& residue) {
+    int ux = tile_index(bx, 0, i[0], T.x), uy = tile_index(bx, 1, i[1], T.y);
+    int uz = NDIM == 3 ? tile_index(bx, 2, i[2], T.z) : 0;
+    const int cx = dir_code(tx, ux, bx.nt[0]);
+    const int cy = dir_code(ty, uy, bx.nt[1]);
+    const int cz = NDIM == 3 ? dir_code(tz, uz, bx.nt[2]) : 0;
+    int k = NDIM == 3 ? (cz * 3 + cy) * 3 + cx : cy * 3 + cx;
+    if (cx < 0 || cy < 0 || cz < 0) {
+        errbits |= ERRBIT_STATE;
+        k = Codes<NDIM>::STAY;
+        ux = tx;
+        uy = ty;
+        uz = tz;
+    }
+    const int lx = i[0] - tile_origin(bx, 0, ux, T.x) + 2;
+    const int ly = i[1] - tile_origin(bx, 1, uy, T.y) + 2;
     int idx = ly * (T.x + 4) + lx;
-    if (NDIM == 3) idx += (ni[2] - tile_origin(bx, 2, dz, T.z) + 2) * (T.x + 4) * (T.y + 4);
-    return idx & (kResidues - 1);
+    if (NDIM == 3) idx += (i[2] - tile_origin(bx, 2, uz, T.z) + 2) * (T.x + 4) * (T.y + 4);
+    residue = idx & (kResidues - 1);
+    return k;
 }
 
 // Code word of a particle for the binning: direction code k (bits 0-4), bank

@@ -303,11 +303,12 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         ni[0] = wrap_shift(ni[0], Pol::drift(e0, k1.u[0], hx), bx.n[0]);
         ni[1] = wrap_shift(ni[1], Pol::drift(e1, k1.u[1], hy), bx.n[1]);
         if (NDIM == 3) ni[2] = wrap_shift(ni[2], Pol::drift(e2, k1.u[2], hz), bx.n[2]);
-        const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits);
+        int res;
+        const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits, res);
         // predicted shift of the next predictor deposit (velocity as now)
         const int p0 = Pol::drift(e0, k1.u[0], hx), p1 = Pol::drift(e1, k1.u[1], hy);
         const int p2 = NDIM == 3 ? Pol::drift(e2, k1.u[2], hz) : 0;
-        a.code[j] = pack_code(k, bank_residue<NDIM>(bx, T, tx, ty, tz, k, ni), shift_class<NDIM>(p0, p1, p2));
+        a.code[j] = pack_code(k, res, shift_class<NDIM>(p0, p1, p2));
         // most particles stay in the tile: one LDS atomic per wave for them
         const uint64_t stays = __ballot(k == Codes<NDIM>::STAY);
         if (k != Codes<NDIM>::STAY) atomicAdd(&s_cnt[k], 1u);
