@@ -26,7 +26,7 @@ def to_dev(a: np.ndarray, dev="cuda"):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-class GpuRun:
+class DeviceRun:
     """One or more workloads as the boxes of one GPU context."""
 
     def __init__(self, wls, tile=(0, 0, 0), precision=0):

@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import GpuRun, oracle_run  # noqa: E402
+from gpu_helpers import DeviceRun, oracle_run  # noqa: E402
 
 
 def _need_gpu():
@@ -24,8 +24,8 @@ def _boxes(n=10, seed0=900):
 def test_batched_fp64_graph_replays_match_eager_and_oracle():
     _need_gpu()
     wls = _boxes()
-    eager = GpuRun(wls)
-    graph = GpuRun(wls)
+    eager = DeviceRun(wls)
+    graph = DeviceRun(wls)
     oracles = [oracle_run(w) for w in wls]
     stream = torch.cuda.Stream()
     dts = [w.dt for w in wls]
@@ -51,8 +51,8 @@ def test_batched_fp64_graph_replays_match_eager_and_oracle():
 def test_batched_fp32_each_box_equals_its_single_box_run():
     _need_gpu()
     wls = _boxes(n=8, seed0=950)
-    many = GpuRun(wls, precision=1)
-    singles = [GpuRun(w, precision=1) for w in wls]
+    many = DeviceRun(wls, precision=1)
+    singles = [DeviceRun(w, precision=1) for w in wls]
     stream = torch.cuda.Stream()
     dts = [w.dt for w in wls]
     with torch.cuda.stream(stream):
@@ -74,7 +74,7 @@ def test_graph_rejects_odd_steps_and_default_stream():
     _need_gpu()
     from paper_1412_1087_amd import mhdpic as M
     wl = W.gyro2d(nx=16, ny=16, ppc=2, seed=960)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     s = torch.cuda.Stream()
     with pytest.raises(M.MhdpicError):
         g.ctx.step_graph(g.B, g.vg, g.rho, [wl.dt], 3, s)
@@ -92,7 +92,7 @@ def test_autotune_picks_a_compiled_shape_that_stays_exact():
                           to_dev(wl.B), to_dev(wl.vg), to_dev(wl.rho), wl.dt, n_steps=4)
     assert tile in [(8, 4, 4), (8, 8, 4), (4, 4, 4), (16, 4, 4)]
     assert ms > 0
-    g = GpuRun(wl, tile=tile)
+    g = DeviceRun(wl, tile=tile)
     o = oracle_run(wl)
     g.step(2)
     o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
@@ -103,8 +103,8 @@ def test_autotune_picks_a_compiled_shape_that_stays_exact():
 def test_graph_subcycled_replays_match_eager_and_oracle():
     _need_gpu()
     wls = _boxes(n=4, seed0=980)
-    eager = GpuRun(wls)
-    graph = GpuRun(wls)
+    eager = DeviceRun(wls)
+    graph = DeviceRun(wls)
     oracles = [oracle_run(w) for w in wls]
     stream = torch.cuda.Stream()
     dts = [w.dt for w in wls]
@@ -130,7 +130,7 @@ def test_graph_and_eager_calls_mix_in_one_context():
     (it re-uploads the step constants and recaptures)."""
     _need_gpu()
     wl = W.gyro2d(nx=24, ny=20, ppc=4, seed=990)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     stream = torch.cuda.Stream()
     dt1, dt2 = wl.dt, 0.7 * wl.dt
@@ -155,7 +155,7 @@ def test_user_captured_step_replays_match_the_oracle():
     with eager steps and synchronisations between the replays."""
     _need_gpu()
     wl = W.gyro2d(nx=20, ny=24, ppc=4, seed=995)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     g.step(2)                      # uploads this dt before the capture
     o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)

@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import GpuRun, oracle_run  # noqa: E402
+from gpu_helpers import DeviceRun, oracle_run  # noqa: E402
 
 REL = 1e-12
 
@@ -63,7 +63,7 @@ def test_degenerate_fields_and_particles(ndim):
     far = x[0] > 0.75 * nx * wl.box.dx[0]
     x[0, far] -= 0.5 * nx * wl.box.dx[0]
     wl.x, wl.v, wl.m = x, v, m
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     (D0,) = g.deposits()
     assert (D0 == o.D).all(), "initial deposit"
@@ -89,7 +89,7 @@ def test_largest_grid_extents(shape):
     for d in range(nd):
         x[d, :16] = (wl.box.n[d] - 0.5 - 0.3 * np.arange(16) / 16.0) * wl.box.dx[d]
     wl.x = x
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     for rep in range(2):
         g.step(1)

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 from oracle import oracle as O  # noqa: E402
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import GpuRun, oracle_box, oracle_run  # noqa: E402
+from gpu_helpers import DeviceRun, oracle_box, oracle_run  # noqa: E402
 
 
 def _need_gpu():
@@ -26,7 +26,7 @@ def test_feedback_matches_oracle_bitwise(which):
         wl = W.bell3d(n=(12, 10, 9), ppc=4, seed=1300, hall=1)
     else:
         wl = W.gyro2d(nx=24, ny=20, ppc=5, seed=1301)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     for k in range(2):
         out_g = g.ctx.feedback(g.B, g.vg, g.rho).cpu().numpy()
@@ -43,7 +43,7 @@ def test_feedback_of_boxes_with_and_without_hall():
     wa = W.gyro2d(nx=16, ny=18, ppc=3, seed=1310)
     wb = W.gyro2d(nx=20, ny=16, ppc=4, seed=1311)
     wb.box.hall = 1
-    g = GpuRun([wa, wb])
+    g = DeviceRun([wa, wb])
     out = g.ctx.feedback(g.B, g.vg, g.rho).cpu().numpy()
     for b, w in enumerate([wa, wb]):
         sl = slice(g.cell_off[b], g.cell_off[b + 1])

@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 from oracle import oracle as O  # noqa: E402
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import GpuRun, oracle_box, oracle_run  # noqa: E402
+from gpu_helpers import DeviceRun, oracle_box, oracle_run  # noqa: E402
 
 REL = 1e-12
 EPS32 = 2.0 ** -24
@@ -62,7 +62,7 @@ def _flat(c, n):
 def _sampled_cell_parity(wl, cells):
     nd = wl.box.ndim
     n = wl.box.n
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     (D0,) = g.deposits()
     g.step(1)
     (D1,) = g.deposits()
@@ -134,7 +134,7 @@ def test_full_size_batched_graph_sampled_boxes():
     pick = sorted({int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), 3, 77, 200})
     stream = torch.cuda.Stream()
     dts = [w.dt for w in wls]
-    g = GpuRun(wls)
+    g = DeviceRun(wls)
     with torch.cuda.stream(stream):
         g.ctx.step_graph(g.B, g.vg, g.rho, dts, 2, stream)
     stream.synchronize()
@@ -149,7 +149,7 @@ def test_full_size_batched_graph_sampled_boxes():
         assert np.abs(P[b][1] - o.v).max() <= REL * np.abs(o.v).max(), f"box {b}"
     del g
     torch.cuda.empty_cache()
-    g32 = GpuRun(wls, precision=1)
+    g32 = DeviceRun(wls, precision=1)
     with torch.cuda.stream(stream):
         g32.ctx.step_graph(g32.B, g32.vg, g32.rho, dts, 2, stream)
     stream.synchronize()
@@ -157,7 +157,7 @@ def test_full_size_batched_graph_sampled_boxes():
     D32 = g32.deposits()
     P32 = g32.particles()
     for b in pick:
-        s = GpuRun(wls[b], precision=1)
+        s = DeviceRun(wls[b], precision=1)
         s.step(2)
         (Ds,) = s.deposits()
         ((xs, vs),) = s.particles()
@@ -173,7 +173,7 @@ def test_full_size_precision_form_properties():
     wl = W.bell3d(n=128, ppc=32, seed=4001, n_steps=100)
     v0 = wl.v.astype(np.float32).astype(np.float64)
     m32 = wl.m.astype(np.float32).astype(np.float64)
-    g32 = GpuRun(wl, precision=1)
+    g32 = DeviceRun(wl, precision=1)
     g32.step(1)
     (D32,) = g32.deposits()
     ((x32, v32),) = g32.particles()
@@ -185,7 +185,7 @@ def test_full_size_precision_form_properties():
         amounts = (-(m32 * (v32[d] - v0[d]))) * S
         want = np.rint(amounts).astype(np.int64).sum()     # wraps mod 2^64 like the grid sums
         assert D32[4 + d].sum() == want, d
-    g64 = GpuRun(wl)
+    g64 = DeviceRun(wl)
     g64.step(1)
     (D64,) = g64.deposits()
     ((x64, v64),) = g64.particles()

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import GpuRun, oracle_run, to_dev  # noqa: E402
+from gpu_helpers import DeviceRun, oracle_run, to_dev  # noqa: E402
 
 REL = 1e-12
 
@@ -37,7 +37,7 @@ def _assert_states(wl, sysO, x_g, v_g):
 
 def _parity(wl, n_steps=1, tile=(0, 0, 0), steps_per_call=1):
     _need_gpu()
-    g = GpuRun(wl, tile=tile)
+    g = DeviceRun(wl, tile=tile)
     o = oracle_run(wl)
     (D0,) = g.deposits()
     assert (D0 == o.D).all(), "init deposit differs"
@@ -154,7 +154,7 @@ def test_parity_multi_box_context():
     _need_gpu()
     wls = [W.gyro2d(nx=17, ny=40, ppc=3, seed=20), W.gyro2d(nx=8, ny=8, ppc=11, seed=21),
            W.gyro2d(nx=64, ny=16, ppc=2, seed=22)]
-    g = GpuRun(wls)
+    g = DeviceRun(wls)
     os_ = [oracle_run(w) for w in wls]
     for st in range(2):
         g.step(1)
@@ -175,7 +175,7 @@ def test_empty_box_and_no_particles():
         setattr(empty, k, getattr(empty, k)[:, :0])
     empty.m = empty.m[:0]
     empty.qm = empty.qm[:0]
-    g = GpuRun([wl, empty])
+    g = DeviceRun([wl, empty])
     o = oracle_run(wl)
     g.step(2)
     o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
@@ -187,7 +187,7 @@ def test_empty_box_and_no_particles():
 def test_deposit_read_reset_and_accumulate():
     _need_gpu()
     wl = W.gyro2d(nx=12, ny=12, ppc=4, seed=25)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     g.step(2)
     o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
@@ -203,7 +203,7 @@ def test_deposit_read_reset_and_accumulate():
 def test_negative_dt_reverses():
     _need_gpu()
     wl = W.gyro2d(nx=12, ny=12, ppc=4, seed=26)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     ((x0, v0),) = g.particles()
     g.step(10)
     g.step(10, dts=[-wl.dt])
@@ -219,7 +219,7 @@ def test_move_limit_rejected():
     _need_gpu()
     from paper_1412_1087_amd import mhdpic as M
     wl = W.gyro2d(nx=8, ny=8, ppc=1, seed=27)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     with pytest.raises(M.MhdpicError) as e:
         g.ctx.step(g.B, g.vg, g.rho, [0.2], 1)  # C*dt/dx = 4 > 2
     assert e.value.code == M.ERANGE
@@ -232,7 +232,7 @@ def test_nonfinite_velocity_rejected_at_init():
     wl.v = wl.v.copy()
     wl.v[1, 5] = np.nan
     with pytest.raises(M.MhdpicError) as e:
-        GpuRun(wl)
+        DeviceRun(wl)
     assert e.value.code == M.ENONFINITE
 
 
@@ -243,7 +243,7 @@ def test_amount_overflow_flagged():
     wl.m = wl.m.copy()
     wl.m[3] = 1e5  # (q/mc) m 2^40 > 2^51
     with pytest.raises(M.MhdpicError) as e:
-        GpuRun(wl)
+        DeviceRun(wl)
     assert e.value.code == M.ERANGE
 
 
@@ -262,7 +262,7 @@ def test_parity_many_steps_stays_bit_exact():
 def test_parity_dt_changes_between_calls():
     _need_gpu()
     wl = W.gyro2d(nx=20, ny=20, ppc=5, seed=33)
-    g = GpuRun(wl)
+    g = DeviceRun(wl)
     o = oracle_run(wl)
     for f in (1.0, 0.5, -0.7, 1.0):
         g.step(3, dts=[f * wl.dt])

@@ -9,14 +9,14 @@ pytestmark = pytest.mark.gpu
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 from paper_1412_1087_amd.mhdpic import MhdpicError  # noqa: E402
 
-from gpu_helpers import GpuRun  # noqa: E402
+from gpu_helpers import DeviceRun  # noqa: E402
 
 
 def test_timing_selects_phases():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1412_1087_amd import mhdpic as M
-    g = GpuRun(W.gyro2d(nx=16, ny=16, ppc=4, seed=40))
+    g = DeviceRun(W.gyro2d(nx=16, ny=16, ppc=4, seed=40))
     ctx = g.ctx
     ctx.timing(True, phases=("push",))
     g.step(3)
