@@ -59,7 +59,8 @@ enum {
     MHDPIC_ENOMEM = -2,     /* workspace too small */
     MHDPIC_EDEVICE = -3,    /* a HIP call failed */
     MHDPIC_ERANGE = -4,     /* time step over the move limit, a deposit amount
-                               |V| >= 2^51 quanta, or a grid/particle count
+                               |V| >= 2^51 quanta, a position whose (x-x0)/dx lies
+                               outside [-2^31, 2^31), or a grid/particle count
                                beyond the library's index limits */
     MHDPIC_ENONFINITE = -5, /* a position or velocity is not finite */
     MHDPIC_ESTATE = -6,     /* internal consistency check failed */

@@ -392,6 +392,8 @@ int oracle_init(const oracle_box* bx, oracle_particles* P, const double* x, cons
             double s = (x[d * N + j] - bx->x0[d]) / bx->dx[d];
             double fl = floor(s);
             if (!isfinite(s)) return ORACLE_ENONFINITE;
+            /* the cell count along the box from x0 must fit a 32-bit int */
+            if (!(fl >= -2147483648.0 && fl < 2147483648.0)) return ORACLE_ERANGE;
             dl[d] = (s - fl) - 0.5;
             i[d] = wrap_index((int)(int64_t)fl, bx->n[d]);
         }

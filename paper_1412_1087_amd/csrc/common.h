@@ -9,7 +9,8 @@ namespace mhdpic {
 // Error bits latched by kernels in the device error word.
 enum : uint32_t {
     ERRBIT_NONFINITE = 1u,  // a velocity or position became non-finite
-    ERRBIT_RANGE = 2u,      // a deposit amount |V| >= 2^51 quanta
+    ERRBIT_RANGE = 2u,      // a deposit amount |V| >= 2^51 quanta, or a position
+                            // more than 2^31 cells from the box origin
     ERRBIT_STATE = 4u,      // a particle was not inside the tile it was binned to
 };
 

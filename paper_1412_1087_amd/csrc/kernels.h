@@ -85,13 +85,15 @@ __global__ void k_init_convert(PS P, const double* __restrict__ x, const double*
     int b = find_box(part_off, nb, j);
     const BoxDev& bx = boxes[b];
     int ic[3] = {0, 0, 0};
-    bool bad = false;
+    bool bad = false, far = false;
     for (int d = 0; d < NDIM; ++d) {
         double s = (x[d * N + j] - bx.x0[d]) / bx.dx[d];
         double fl = floor(s);
         if (!isfinite(s)) bad = true;
+        // the cell count from x0 must fit a 32-bit int
+        else if (!(fl >= -2147483648.0 && fl < 2147483648.0)) far = true;
         double off = (s - fl) - 0.5;
-        ic[d] = bad ? 0 : pmod((int)(long long)fl, bx.n[d]);
+        ic[d] = (bad || far) ? 0 : pmod((int)(long long)fl, bx.n[d]);
         T o = (T)off;
         if (o >= (T)0.5) {  // binary32 rounding can reach the upper edge
             o = o - (T)1;
@@ -106,6 +108,7 @@ __global__ void k_init_convert(PS P, const double* __restrict__ x, const double*
     }
     if (!isfinite(m[j]) || !isfinite(qm[j])) bad = true;
     if (bad) latch(err, ERRBIT_NONFINITE);
+    if (far) latch(err, ERRBIT_RANGE);
     P.cell[j] = pack_cell<NDIM>(ic[0], ic[1], ic[2]);
     P.m[j] = m[j];
     P.qm[j] = qm[j];

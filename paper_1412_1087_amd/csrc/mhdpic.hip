@@ -306,7 +306,9 @@ int code_of(uint32_t bits) {
 
 const char* msg_of(uint32_t bits) {
     if (bits & ERRBIT_NONFINITE) return "device: a position or velocity is not finite";
-    if (bits & ERRBIT_RANGE) return "device: a deposit amount reached 2^51 quanta";
+    if (bits & ERRBIT_RANGE)
+        return "device: a deposit amount reached 2^51 quanta, or a position lies 2^31 or more "
+               "cells from its box origin";
     if (bits & ERRBIT_STATE) return "device: a particle was outside its tile";
     return "";
 }

@@ -136,6 +136,13 @@ def _perturbation(box: BoxSpec, rng, m_max: int, rms: float) -> np.ndarray:
     return np.ascontiguousarray(fld)
 
 
+def _cell_volume(box: BoxSpec) -> float:
+    v = 1.0
+    for d in range(box.ndim):
+        v = v * box.dx[d]
+    return v
+
+
 def _isotropic(rng, mag: np.ndarray) -> np.ndarray:
     n = mag.shape[0]
     mu = rng.uniform(-1.0, 1.0, size=n)
@@ -166,8 +173,9 @@ def choose_dt(box: BoxSpec, v: np.ndarray, qm: np.ndarray, B: np.ndarray, phase:
 # workloads
 # --------------------------------------------------------------------------
 
-def gyro2d(nx=32, ny=32, ppc=16, seed=1001, C=20.0, n_steps=100, eta=2e-3) -> Workload:
-    box = BoxSpec(ndim=2, n=(nx, ny, 1), C=C, hall=0)
+def gyro2d(nx=32, ny=32, ppc=16, seed=1001, C=20.0, n_steps=100, eta=2e-3,
+           dx=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0)) -> Workload:
+    box = BoxSpec(ndim=2, n=(nx, ny, 1), dx=tuple(dx), x0=tuple(x0), C=C, hall=0)
     rng = np.random.default_rng(seed)
     nc = box.n_cells
     rho = np.ones(nc)
@@ -181,17 +189,19 @@ def gyro2d(nx=32, ny=32, ppc=16, seed=1001, C=20.0, n_steps=100, eta=2e-3) -> Wo
     u = _isotropic(rng, umag)
     gam = 1.0 / np.sqrt(1.0 - (umag / C) ** 2)
     v = u * gam[None, :]
-    m = np.full(N, eta * 1.0 * 1.0 / ppc)
+    # CR mass density eta * rho: m = eta rho dV / ppc
+    m = np.full(N, eta * _cell_volume(box) / ppc)
     qm = np.ones(N)
     dt = choose_dt(box, v, qm, B)
     return Workload("gyro2d", box, np.ascontiguousarray(B), vg, rho, x, np.ascontiguousarray(v), m,
                     qm, dt, n_steps, dict(ppc=ppc, seed=seed))
 
 
-def bell3d(n=64, ppc=16, seed=2001, C=20.0, n_steps=200, ncr_frac=0.05, hall=1) -> Workload:
+def bell3d(n=64, ppc=16, seed=2001, C=20.0, n_steps=200, ncr_frac=0.05, hall=1,
+           dx=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0)) -> Workload:
     if isinstance(n, int):
         n = (n, n, n)
-    box = BoxSpec(ndim=3, n=tuple(n), C=C, hall=hall)
+    box = BoxSpec(ndim=3, n=tuple(n), dx=tuple(dx), x0=tuple(x0), C=C, hall=hall)
     rng = np.random.default_rng(seed)
     nc = box.n_cells
     rho = np.ones(nc)
@@ -206,7 +216,7 @@ def bell3d(n=64, ppc=16, seed=2001, C=20.0, n_steps=200, ncr_frac=0.05, hall=1) 
     v[0] += gD * vD
     qm = np.ones(N)
     # n_CR = (q/mc) m ppc / dV = ncr_frac * (q/mc)_g rho
-    m = np.full(N, ncr_frac * 1.0 * 1.0 / ppc)
+    m = np.full(N, ncr_frac * _cell_volume(box) / ppc)
     dt = choose_dt(box, v, qm, B)
     return Workload("bell3d", box, np.ascontiguousarray(B), vg, rho, x, np.ascontiguousarray(v), m,
                     qm, dt, n_steps, dict(ppc=ppc, seed=seed))
