@@ -47,7 +47,18 @@
  *   - the n_CR, J_CR arrays are refreshed every step at the particle
  *     positions x^(n+1) (the predictor input of the next step); the -dM,
  *     -dE_k arrays accumulate over steps until the caller reads and clears them;
- *   - all boundaries are periodic.
+ *   - faces (Sec. 5: a conducting wall, an inflow boundary) are periodic,
+ *     reflecting or absorbing per axis and side.  A particle that crosses a
+ *     reflecting face during a half drift is mirrored back (offset negated,
+ *     that axis's four-velocity and three-velocity negated); one that crosses
+ *     an absorbing face leaves the box: crossed in the first half drift it
+ *     deposits nothing, in the second it has deposited -dM, -dE_k but
+ *     deposits no n_CR, J_CR.  At a non-periodic face a stencil cell beyond
+ *     the box is its mirror image inside (cell -1-k is cell k, cell n+k is
+ *     cell n-1-k): gathers read the mirror cell's field and deposits land on
+ *     it, so every amount stays in the box;
+ *   - particles can be added (each deposits its n_CR, J_CR at once) and
+ *     removed (its n_CR, J_CR at its current position is taken back).
  */
 #include <math.h>
 #include <stdint.h>
@@ -188,6 +199,20 @@ static int wrap_index(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+static int periodic_axis(const oracle_box* bx, int d) {
+    return bx->bc[d][0] == ORACLE_PERIODIC;
+}
+
+/* Cell index along axis d for an index that may lie one or two cells beyond
+ * the box: wrapped on a periodic axis, mirrored at a non-periodic face. */
+static int map_index(const oracle_box* bx, int d, int i) {
+    int n = bx->n[d];
+    if (periodic_axis(bx, d)) return wrap_index(i, n);
+    if (i < 0) return -1 - i;
+    if (i >= n) return 2 * n - 1 - i;
+    return i;
+}
+
 static int64_t cell_linear(const oracle_box* bx, const int c[3]) {
     int64_t z = bx->ndim == 3 ? c[2] : 0;
     return (z * bx->n[1] + c[1]) * bx->n[0] + c[0];
@@ -211,9 +236,9 @@ static void make_stencil(const oracle_box* bx, const int i[3], const double dl[3
         for (int oy = -1; oy <= 1; ++oy)
             for (int ox = -1; ox <= 1; ++ox) {
                 int c[3];
-                c[0] = wrap_index(i[0] + ox, bx->n[0]);
-                c[1] = wrap_index(i[1] + oy, bx->n[1]);
-                c[2] = bx->ndim == 3 ? wrap_index(i[2] + oz, bx->n[2]) : 0;
+                c[0] = map_index(bx, 0, i[0] + ox);
+                c[1] = map_index(bx, 1, i[1] + oy);
+                c[2] = bx->ndim == 3 ? map_index(bx, 2, i[2] + oz) : 0;
                 st->cell[k] = cell_linear(bx, c);
                 double wxy = w[0][ox + 1] * w[1][oy + 1];
                 st->W[k] = bx->ndim == 3 ? wxy * w[2][oz + 1] : wxy;
@@ -223,34 +248,69 @@ static void make_stencil(const oracle_box* bx, const int i[3], const double dl[3
     st->nk = k;
 }
 
-/* Adds the amount V (already in quanta, i.e. multiplied by 2^frac_bits) to the
- * stencil cells of D.  Integers wrap modulo 2^64 (unsigned arithmetic).
- * Returns MHDPIC_ORACLE_ERANGE if |V| >= 2^51. */
-static int deposit_amount(int64_t* D, const stencil* st, double V) {
+/* Adds sign times the amount V (already in quanta, i.e. multiplied by
+ * 2^frac_bits) to the stencil cells of D: each cell receives its rounded
+ * share, so taking a deposit back (sign -1) removes exactly the integers it
+ * added.  Integers wrap modulo 2^64 (unsigned arithmetic).  Returns
+ * ORACLE_ERANGE if |V| >= 2^51. */
+static int deposit_signed(int64_t* D, const stencil* st, double V, int sign) {
     if (!(fabs(V) < 2251799813685248.0)) return ORACLE_ERANGE; /* 2^51 */
     int64_t total = oracle_rne_product(V, 1.0);
     uint64_t rest = 0;
     for (int k = 0; k < st->nk; ++k) {
         if (k == st->centre) continue;
         int64_t q = oracle_rne_product(st->W[k], V);
-        D[st->cell[k]] = (int64_t)((uint64_t)D[st->cell[k]] + (uint64_t)q);
+        uint64_t a = sign > 0 ? (uint64_t)q : (uint64_t)0 - (uint64_t)q;
+        D[st->cell[k]] = (int64_t)((uint64_t)D[st->cell[k]] + a);
         rest += (uint64_t)q;
     }
     uint64_t qc = (uint64_t)total - rest;
-    D[st->cell[st->centre]] = (int64_t)((uint64_t)D[st->cell[st->centre]] + qc);
+    uint64_t a = sign > 0 ? qc : (uint64_t)0 - qc;
+    D[st->cell[st->centre]] = (int64_t)((uint64_t)D[st->cell[st->centre]] + a);
     return ORACLE_OK;
 }
 
-/* Moves a particle by u*hdx cells in each dimension and renormalises the
- * offset into [-1/2, 1/2), wrapping the cell index periodically. */
-static void drift(const oracle_box* bx, int i[3], double dl[3], const double u[3],
-                  const double hdx[3]) {
+static int deposit_amount(int64_t* D, const stencil* st, double V) {
+    return deposit_signed(D, st, V, 1);
+}
+
+/* Moves a particle by u*hdx cells along each axis and renormalises the
+ * offset into [-1/2, 1/2).  A cell index that leaves the box wraps on a
+ * periodic axis; at a reflecting face the position is mirrored about the
+ * face (cell -1 at offset d becomes cell 0 at offset -d; cell n becomes cell
+ * n-1) and the axis's components of v and u change sign.  A position exactly
+ * on the upper face mirrors onto itself; it is kept inside at the largest
+ * offset below 1/2.  Returns 1 if the particle crossed an absorbing face (the
+ * remaining axes are then not moved), else 0. */
+static int drift(const oracle_box* bx, int i[3], double dl[3], double u[3], double v[3],
+                 const double hdx[3]) {
     for (int d = 0; d < bx->ndim; ++d) {
+        int n = bx->n[d];
         dl[d] = dl[d] + u[d] * hdx[d];
         while (dl[d] >= 0.5) { dl[d] = dl[d] - 1.0; i[d] += 1; }
         while (dl[d] < -0.5) { dl[d] = dl[d] + 1.0; i[d] -= 1; }
-        i[d] = wrap_index(i[d], bx->n[d]);
+        if (i[d] >= 0 && i[d] < n) continue;
+        if (periodic_axis(bx, d)) {
+            i[d] = wrap_index(i[d], n);
+            continue;
+        }
+        int side = i[d] < 0 ? 0 : 1;
+        if (bx->bc[d][side] == ORACLE_ABSORB) return 1;
+        /* reflect.  A half drift moves less than one cell, so i is -1 or n.
+         * From cell 0 the offset in cell -1 is above -1/2 (strictly, and exactly
+         * so in binary64), so its negation stays below 1/2; at the upper face
+         * the offset in cell n can be exactly -1/2 (the position on the face). */
+        dl[d] = -dl[d];
+        if (side == 0) {
+            i[d] = 0;
+        } else {
+            i[d] = n - 1;
+            if (dl[d] >= 0.5) dl[d] = nextafter(0.5, 0.0);
+        }
+        v[d] = -v[d];
+        u[d] = -u[d];
     }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -355,6 +415,11 @@ static int check_box(const oracle_box* bx) {
     for (int d = 0; d < bx->ndim; ++d) {
         if (bx->n[d] < 1) return ORACLE_EINVAL;
         if (!(bx->dx[d] > 0.0)) return ORACLE_EINVAL;
+        for (int side = 0; side < 2; ++side)
+            if (bx->bc[d][side] < ORACLE_PERIODIC || bx->bc[d][side] > ORACLE_ABSORB) return ORACLE_EINVAL;
+        if ((bx->bc[d][0] == ORACLE_PERIODIC) != (bx->bc[d][1] == ORACLE_PERIODIC)) return ORACLE_EINVAL;
+        /* a mirrored position must land inside: at least two cells */
+        if (bx->bc[d][0] != ORACLE_PERIODIC && bx->n[d] < 2) return ORACLE_EINVAL;
     }
     if (bx->ndim == 2 && bx->n[2] != 1) return ORACLE_EINVAL;
     if (!(bx->C > 0.0)) return ORACLE_EINVAL;
@@ -378,39 +443,82 @@ static int deposit_charge_current(const oracle_box* bx, int64_t* D, int64_t nc, 
     return rc;
 }
 
-int oracle_init(const oracle_box* bx, oracle_particles* P, const double* x, const double* v,
-                const double* m, const double* qm, int64_t* D) {
+/* Converts particles first .. first+N_new-1 of P from global positions x,
+ * four-velocities v (arrays [3][N_new]) and m, qm, and deposits their n_CR,
+ * J_CR into D[0..3].  On a non-periodic axis a position must lie inside the
+ * box (ORACLE_ERANGE otherwise). */
+int oracle_add(const oracle_box* bx, oracle_particles* P, int64_t first, const double* x,
+               const double* v, const double* m, const double* qm, int64_t* D) {
     int rc = check_box(bx);
     if (rc) return rc;
     int64_t N = P->N, nc = n_cells(bx);
+    int64_t Nn = N - first;
     double S = ldexp(1.0, bx->frac_bits);
-    memset(D, 0, sizeof(int64_t) * 8 * (size_t)nc);
-    for (int64_t j = 0; j < N; ++j) {
+    for (int64_t k = 0; k < Nn; ++k) {
+        int64_t j = first + k;
         int i[3] = {0, 0, 0};
         double dl[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < bx->ndim; ++d) {
-            double s = (x[d * N + j] - bx->x0[d]) / bx->dx[d];
+            double s = (x[d * Nn + k] - bx->x0[d]) / bx->dx[d];
             double fl = floor(s);
             if (!isfinite(s)) return ORACLE_ENONFINITE;
             /* the cell count along the box from x0 must fit a 32-bit int */
             if (!(fl >= -2147483648.0 && fl < 2147483648.0)) return ORACLE_ERANGE;
+            if (!periodic_axis(bx, d) && !(fl >= 0.0 && fl < (double)bx->n[d])) return ORACLE_ERANGE;
             dl[d] = (s - fl) - 0.5;
             i[d] = wrap_index((int)(int64_t)fl, bx->n[d]);
         }
-        double vj[3] = {v[j], v[N + j], v[2 * N + j]};
+        double vj[3] = {v[k], v[Nn + k], v[2 * Nn + k]};
         if (!isfinite(vj[0]) || !isfinite(vj[1]) || !isfinite(vj[2])) return ORACLE_ENONFINITE;
         for (int d = 0; d < 3; ++d) {
             P->cell[d * N + j] = i[d];
             P->delta[d * N + j] = dl[d];
             P->v[d * N + j] = vj[d];
         }
-        P->m[j] = m[j];
-        P->qm[j] = qm[j];
+        P->m[j] = m[k];
+        P->qm[j] = qm[k];
+        if (P->alive) P->alive[j] = 1;
         double g, u[3], ek;
         oracle_lorentz(vj, bx->C, &g, u, &ek);
-        rc = deposit_charge_current(bx, D, nc, i, dl, qm[j], m[j], u, S);
+        rc = deposit_charge_current(bx, D, nc, i, dl, qm[k], m[k], u, S);
         if (rc) return rc;
     }
+    return ORACLE_OK;
+}
+
+int oracle_init(const oracle_box* bx, oracle_particles* P, const double* x, const double* v,
+                const double* m, const double* qm, int64_t* D) {
+    int rc = check_box(bx);
+    if (rc) return rc;
+    memset(D, 0, sizeof(int64_t) * 8 * (size_t)n_cells(bx));
+    return oracle_add(bx, P, 0, x, v, m, qm, D);
+}
+
+/* Removes particle j: takes its n_CR, J_CR deposit at its current position
+ * back out of D[0..3] and marks it gone (P->alive must be given). */
+int oracle_remove(const oracle_box* bx, oracle_particles* P, int64_t j, int64_t* D) {
+    int rc = check_box(bx);
+    if (rc) return rc;
+    if (!P->alive || j < 0 || j >= P->N || !P->alive[j]) return ORACLE_EINVAL;
+    int64_t N = P->N, nc = n_cells(bx);
+    int i[3];
+    double dl[3], v[3];
+    for (int d = 0; d < 3; ++d) {
+        i[d] = P->cell[d * N + j];
+        dl[d] = P->delta[d * N + j];
+        v[d] = P->v[d * N + j];
+    }
+    double g, u[3], ek;
+    oracle_lorentz(v, bx->C, &g, u, &ek);
+    stencil st;
+    make_stencil(bx, i, dl, &st);
+    double S = ldexp(1.0, bx->frac_bits);
+    double qmm = P->qm[j] * P->m[j];
+    rc = deposit_signed(D, &st, qmm * S, -1);
+    for (int d = 0; d < 3 && rc == ORACLE_OK; ++d)
+        rc = deposit_signed(D + (1 + d) * nc, &st, (qmm * u[d]) * S, -1);
+    if (rc) return rc;
+    P->alive[j] = 0;
     return ORACLE_OK;
 }
 
@@ -459,6 +567,7 @@ int oracle_step_sub(const oracle_box* bx, oracle_particles* P, const double* B, 
         for (int sub = 0; sub < n_sub; ++sub) {
             const int last = sub == n_sub - 1;
             for (int64_t j = 0; j < N; ++j) {
+                if (P->alive && !P->alive[j]) continue;
                 int i[3];
                 double dl[3], v[3];
                 for (int d = 0; d < 3; ++d) {
@@ -471,8 +580,12 @@ int oracle_step_sub(const oracle_box* bx, oracle_particles* P, const double* B, 
                 double g0, u0[3], ek0;
                 oracle_lorentz(v, C, &g0, u0, &ek0);
 
-                /* drift to x^(n+1/2) */
-                drift(bx, i, dl, u0, hdx);
+                /* drift to x^(n+1/2); through an absorbing face: gone, no deposits */
+                if (drift(bx, i, dl, u0, v, hdx)) {
+                    if (!P->alive) return ORACLE_EINVAL;
+                    P->alive[j] = 0;
+                    continue;
+                }
 
                 /* TSC interpolation of E and B at x^(n+1/2) */
                 stencil sh;
@@ -502,8 +615,13 @@ int oracle_step_sub(const oracle_box* bx, oracle_particles* P, const double* B, 
                 rc = deposit_amount(D + 7 * nc, &sh, (-(m * (ek1 - ek0))) * S);
                 if (rc) return rc;
 
-                /* drift to x^(n+1) */
-                drift(bx, i, dl, u1, hdx);
+                /* drift to x^(n+1); through an absorbing face: gone after the
+                 * corrector deposit, before the predictor one */
+                if (drift(bx, i, dl, u1, vn, hdx)) {
+                    if (!P->alive) return ORACLE_EINVAL;
+                    P->alive[j] = 0;
+                    continue;
+                }
 
                 /* n_CR, J_CR at the end of the MHD step for the next predictor */
                 if (last) {

@@ -11,6 +11,10 @@
 #define MHDPIC_ORACLE_H
 #include <stdint.h>
 
+/* Particle boundary of one face of a box (Sec. 5: a conducting wall at x = 0
+ * and an inflow boundary at x = L_x; periodic otherwise). */
+enum { ORACLE_PERIODIC = 0, ORACLE_REFLECT = 1, ORACLE_ABSORB = 2 };
+
 enum {
     ORACLE_OK = 0,
     ORACLE_EINVAL = -1,
@@ -28,7 +32,8 @@ typedef struct {
     int32_t hall;           /* 1: E = E0 - F_CR/n_g; 0: E = E0 */
     int32_t frac_bits;      /* deposits in units of 2^-frac_bits */
     int32_t max_move_cells; /* a particle moves at most this many cells per step */
-    int32_t pad;
+    int32_t bc[3][2];       /* per axis, low and high face: ORACLE_PERIODIC (both faces or
+                               neither), ORACLE_REFLECT or ORACLE_ABSORB */
 } oracle_box;
 
 typedef struct {
@@ -38,6 +43,8 @@ typedef struct {
     double* v;     /* [3][N] spatial four-velocity gamma*u */
     double* m;     /* [N] CR mass carried by the particle */
     double* qm;    /* [N] (q/mc) of the particle */
+    int32_t* alive; /* [N] 1 while the particle is in the box, 0 once it left through an
+                       absorbing face or was removed; NULL: every particle stays */
 } oracle_particles;
 
 int64_t oracle_rne_product(double a, double b);
@@ -53,6 +60,9 @@ int oracle_feedback(const oracle_box* bx, const double* B, const double* vg, con
                     const int64_t* D, double* out);
 int oracle_init(const oracle_box* bx, oracle_particles* P, const double* x, const double* v,
                 const double* m, const double* qm, int64_t* D);
+int oracle_add(const oracle_box* bx, oracle_particles* P, int64_t first, const double* x,
+               const double* v, const double* m, const double* qm, int64_t* D);
+int oracle_remove(const oracle_box* bx, oracle_particles* P, int64_t j, int64_t* D);
 int oracle_check_dt(const oracle_box* bx, double dt);
 int oracle_step(const oracle_box* bx, oracle_particles* P, const double* B, const double* vg,
                 const double* rho, double dt, int n_steps, int64_t* D, int64_t* nJ_next,

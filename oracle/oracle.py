@@ -20,6 +20,7 @@ SRC = os.path.join(HERE, "mhdpic_oracle.c")
 LIB = os.path.join(HERE, "libmhdpic_oracle.so")
 
 OK, EINVAL, ERANGE, ENONFINITE = 0, -1, -4, -5
+PERIODIC, REFLECT, ABSORB = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -37,13 +38,14 @@ class OracleBox(ct.Structure):
     _fields_ = [("ndim", ct.c_int32), ("n", ct.c_int32 * 3), ("dx", ct.c_double * 3),
                 ("x0", ct.c_double * 3), ("C", ct.c_double), ("qomc_gas", ct.c_double),
                 ("hall", ct.c_int32), ("frac_bits", ct.c_int32),
-                ("max_move_cells", ct.c_int32), ("pad", ct.c_int32)]
+                ("max_move_cells", ct.c_int32), ("bc", ct.c_int32 * 6)]
 
 
 class OracleParticles(ct.Structure):
     _fields_ = [("N", ct.c_int64), ("cell", ct.POINTER(ct.c_int32)),
                 ("delta", ct.POINTER(ct.c_double)), ("v", ct.POINTER(ct.c_double)),
-                ("m", ct.POINTER(ct.c_double)), ("qm", ct.POINTER(ct.c_double))]
+                ("m", ct.POINTER(ct.c_double)), ("qm", ct.POINTER(ct.c_double)),
+                ("alive", ct.POINTER(ct.c_int32))]
 
 
 _lib = None
@@ -74,6 +76,12 @@ def lib():
         L.oracle_init.restype = ct.c_int
         L.oracle_init.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), dp, dp, dp,
                                   dp, i64p]
+        L.oracle_add.restype = ct.c_int
+        L.oracle_add.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), ct.c_int64,
+                                 dp, dp, dp, dp, i64p]
+        L.oracle_remove.restype = ct.c_int
+        L.oracle_remove.argtypes = [ct.POINTER(OracleBox), ct.POINTER(OracleParticles), ct.c_int64,
+                                    i64p]
         L.oracle_check_dt.restype = ct.c_int
         L.oracle_check_dt.argtypes = [ct.POINTER(OracleBox), ct.c_double]
         L.oracle_step.restype = ct.c_int
@@ -163,6 +171,8 @@ class Box:
     hall: int = 0
     frac_bits: int = 40
     max_move_cells: int = 2
+    # per axis (low, high): PERIODIC, REFLECT or ABSORB
+    bc: tuple = ((PERIODIC, PERIODIC), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC))
 
     @property
     def n_cells(self) -> int:
@@ -183,7 +193,7 @@ class Box:
         b.hall = int(self.hall)
         b.frac_bits = int(self.frac_bits)
         b.max_move_cells = int(self.max_move_cells)
-        b.pad = 0
+        b.bc = (ct.c_int32 * 6)(*[int(f) for ax in self.bc for f in ax])
         return b
 
 
@@ -199,33 +209,74 @@ class System:
     Arrays follow the [comp][N] / [comp][cells] layout; grid arrays are
     flattened with x fastest.  ``D`` holds the 8 deposit channels:
     n_CR, J_CR (x,y,z) at the current positions, then the accumulated
-    -dM (x,y,z) and -dE_k.
+    -dM (x,y,z) and -dE_k.  Particle j keeps index j for its whole life;
+    ``alive[j]`` is 0 once it has left through an absorbing face or been
+    removed.  Added particles take the next indices.
     """
 
     def __init__(self, box: Box, x, v, m, qm):
         self.box = box
         self._cb = box.c_struct()
-        x = np.ascontiguousarray(x, dtype=np.float64).reshape(3, -1)
-        v = np.ascontiguousarray(v, dtype=np.float64).reshape(3, -1)
-        N = x.shape[1]
-        self.N = N
-        self.cell = np.zeros((3, N), dtype=np.int32)
-        self.delta = np.zeros((3, N), dtype=np.float64)
-        self.v = np.zeros((3, N), dtype=np.float64)
-        self.m = np.zeros(N, dtype=np.float64)
-        self.qm = np.zeros(N, dtype=np.float64)
         nc = box.n_cells
+        self.N = 0
+        self.cell = np.zeros((3, 0), dtype=np.int32)
+        self.delta = np.zeros((3, 0), dtype=np.float64)
+        self.v = np.zeros((3, 0), dtype=np.float64)
+        self.m = np.zeros(0, dtype=np.float64)
+        self.qm = np.zeros(0, dtype=np.float64)
+        self.alive = np.zeros(0, dtype=np.int32)
         self.D = np.zeros((8, nc), dtype=np.int64)
         self._nJ = np.zeros((4, nc), dtype=np.int64)
         self.E = np.zeros((3, nc), dtype=np.float64)
+        self._add(x, v, m, qm, init=True)
+
+    def _grow(self, k: int):
+        N = self.N + k
+        def ext(a, shape):
+            b = np.zeros(shape, dtype=a.dtype)
+            if a.ndim == 2:
+                b[:, :self.N] = a
+            else:
+                b[:self.N] = a
+            return b
+        self.cell = ext(self.cell, (3, N))
+        self.delta = ext(self.delta, (3, N))
+        self.v = ext(self.v, (3, N))
+        self.m = ext(self.m, (N,))
+        self.qm = ext(self.qm, (N,))
+        self.alive = ext(self.alive, (N,))
+        self.N = N
         self._P = OracleParticles(N, _i32p(self.cell), _dp(self.delta), _dp(self.v), _dp(self.m),
-                                  _dp(self.qm))
+                                  _dp(self.qm), _i32p(self.alive))
+
+    def _add(self, x, v, m, qm, init=False):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(3, -1)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(3, -1)
         m = np.ascontiguousarray(m, dtype=np.float64)
         qm = np.ascontiguousarray(qm, dtype=np.float64)
-        rc = lib().oracle_init(ct.byref(self._cb), ct.byref(self._P), _dp(x), _dp(v), _dp(m),
-                               _dp(qm), _i64p(self.D))
+        first = self.N
+        self._grow(x.shape[1])
+        if init:
+            rc = lib().oracle_init(ct.byref(self._cb), ct.byref(self._P), _dp(x), _dp(v), _dp(m),
+                                   _dp(qm), _i64p(self.D))
+        else:
+            rc = lib().oracle_add(ct.byref(self._cb), ct.byref(self._P), first, _dp(x), _dp(v),
+                                  _dp(m), _dp(qm), _i64p(self.D))
         if rc:
             raise OracleError(rc)
+        return np.arange(first, self.N)
+
+    def inject(self, x, v, m, qm):
+        """Adds particles (global positions, four-velocities); their n_CR, J_CR
+        join D[0..3].  Returns their indices."""
+        return self._add(x, v, m, qm)
+
+    def remove(self, idx):
+        """Removes particles: their n_CR, J_CR leave D[0..3]."""
+        for j in np.atleast_1d(idx):
+            rc = lib().oracle_remove(ct.byref(self._cb), ct.byref(self._P), int(j), _i64p(self.D))
+            if rc:
+                raise OracleError(rc)
 
     def step(self, B, vg, rho, dt: float, n_steps: int = 1, n_sub: int = 1):
         """n_steps MHD steps of dt, each of n_sub particle steps of dt/n_sub
