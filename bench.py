@@ -55,6 +55,7 @@ DATA_NOTE = {
     "shock2d": "synthetic (seeded; shapes of the paper's 2D shock runs: upstream/downstream "
                "gas, CR band near the shock)",
     "gyro2d": "synthetic (seeded; the paper's gyration-test settings on a 32x32 box)",
+    "bell3d128": "synthetic (seeded; the Bell-instability test box at 128^3, 32 per cell)",
 }
 
 
@@ -69,6 +70,9 @@ def make_workload(name: str):
     elif name == "gyro2d":
         wl = W.gyro2d()
         label = "gyro2d-32x32-ppc16"
+    elif name == "bell3d128":
+        wl = W.bell3d(n=128, ppc=32, seed=4001, n_steps=100)
+        label = "bell3d-128^3-ppc32-hall"
     else:
         raise SystemExit(f"unknown workload {name}")
     return wl, label
@@ -237,6 +241,64 @@ def run_strip_form(steps: int, warmup: int):
     return out
 
 
+def run_shock_wall_form(steps: int, warmup: int):
+    """The particle side of the Sec. 5 shock set-up: a 2D box of 8192 x 256
+    cells of 12 ion inertial lengths with a conducting (reflecting) wall at
+    x = 0 and an inflow (absorbing) face at x = L_x, the downstream gas at rest
+    behind the front and the upstream flow at -v0, 2M CRs around the front,
+    and CRs injected at the moving front every step (mhdpic_inject, tagged
+    with the injection time, 4 per cell of swept gas).  Throughput counts the
+    particle updates of the timed steps; the time includes the injections."""
+    import torch
+    from paper_1412_1087_amd import mhdpic as M
+    from paper_1412_1087_amd import workloads as W
+    dev = torch.device("cuda:0")
+    st = W.shock_wall2d(nx=8192, ny=256, front_cell=2048)
+    N0 = 2_000_000
+    x, v, m, qm, _ = W.shock_population(st, N0, seed=7002)
+    per_step = max(1, int(round(4 * st.box.n[1] * st.v_sh * st.dt / st.box.dx[0])))
+    total = warmup + steps
+    batches = [W.shock_injection(st, per_step, k * st.dt, seed=7100 + k) for k in range(total)]
+    cap = N0 + per_step * total + 1024
+    box = M.Box(ndim=2, n=st.box.n, dx=st.box.dx, x0=st.box.x0, C=st.box.C, hall=0,
+                boundary=st.boundary, capacity=cap)
+    B, vg, rho = _to(dev, st.B), _to(dev, st.vg), _to(dev, st.rho)
+    ctx = M.Context([box], [N0], *(_to(dev, a) for a in (x, v, m, qm)))
+    dbat = [tuple(_to(dev, a) for a in b) for b in batches]
+    torch.cuda.synchronize()
+
+    def run(ks):
+        inj = 0.0
+        for k in ks:
+            bx, bv, bm, bq, bt = dbat[k]
+            t0 = time.perf_counter()
+            ctx.inject([bx.shape[1]], bx, bv, bm, bq, bt)
+            inj += time.perf_counter() - t0
+            ctx.step(B, vg, rho, st.dt, 1)
+        return inj
+
+    run(list(range(warmup)))
+    torch.cuda.synchronize()
+    n_start = sum(ctx.counts())
+    t0 = time.perf_counter()
+    inj = run(list(range(warmup, total)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_end = sum(ctx.counts())
+    ctx.check()
+    ctx.destroy()
+    n_upd = 0.5 * (n_start + n_end) * steps
+    out = {"workload": "shockwall2d-8192x256-2M", "particles_start": n_start, "particles_end": n_end,
+           "injected_per_step": per_step, "steps": steps,
+           "value": round(n_upd / wall, 1), "unit": "particle-updates/s",
+           "ms_per_step": round(1e3 * wall / steps, 4),
+           "inject_ms_per_step": round(1e3 * inj / steps, 4),
+           "note": "wall clock of inject + step per step (each inject waits for the stream)"}
+    log(f"shock wall: {out['value']:.4g}/s, {out['ms_per_step']} ms/step, "
+        f"inject {out['inject_ms_per_step']} ms/step")
+    return out
+
+
 FEEDBACK_BYTES_PER_CELL = 168  # read n_CR, J_CR (32), B, v_g (48), rho (8); write 10 doubles
 
 
@@ -392,23 +454,108 @@ def run_batched_form(steps: int):
 # CPU baseline: the oracle on a bounded sample
 # --------------------------------------------------------------------------
 
-def run_cpu_baseline(wl, label: str, sample_div: int = 8, steps: int = 6):
+def _oracle_box(wl):
+    from oracle import oracle as O
+    return O.Box(ndim=wl.box.ndim, n=tuple(wl.box.n), dx=tuple(wl.box.dx), x0=tuple(wl.box.x0),
+                 C=wl.box.C, qomc_gas=wl.box.qomc_gas, hall=wl.box.hall,
+                 frac_bits=wl.box.frac_bits, max_move_cells=wl.box.max_move_cells)
+
+
+def _oracle_part(conn, wl, idx, pin):
+    """Child process: the oracle on one disjoint subset of the particles.  Each
+    step it receives the n_CR, J_CR of all subsets (the Hall term's E depends
+    on every particle), steps once and returns its own n_CR, J_CR, its
+    accumulated -dM, -dE_k and the seconds the step took."""
+    from oracle import oracle as O
+    if pin is not None:
+        os.sched_setaffinity(0, {pin})
+    sysO = O.System(_oracle_box(wl), wl.x[:, idx].copy(), wl.v[:, idx].copy(), wl.m[idx].copy(),
+                    wl.qm[idx].copy())
+    conn.send(sysO.D[:4].copy())
+    while True:
+        nJ = conn.recv()
+        if nJ is None:
+            break
+        sysO.D[:4] = nJ
+        t0 = time.perf_counter()
+        sysO.step(wl.B, wl.vg, wl.rho, wl.dt, 1)
+        conn.send((sysO.D.copy(), time.perf_counter() - t0))
+    conn.close()
+
+
+def _oracle_parallel(wl, subsets, steps, pins):
+    """The oracle over disjoint particle subsets, one process each, with the
+    n_CR, J_CR summed over the subsets before every step.  Returns the summed
+    deposits and the wall seconds of the slowest subset per step, summed."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")  # before the GPU is touched in this process
+    procs, conns = [], []
+    for k, idx in enumerate(subsets):
+        a, b = ctx.Pipe()
+        pr = ctx.Process(target=_oracle_part, args=(b, wl, idx, pins[k % len(pins)] if pins else None))
+        pr.start()
+        procs.append(pr)
+        conns.append(a)
+    nJ = sum(c.recv() for c in conns)
+    wall = 0.0
+    acc = None
+    for _ in range(steps):
+        for c in conns:
+            c.send(nJ)
+        outs = [c.recv() for c in conns]
+        Ds = sum(o[0] for o in outs)
+        wall += max(o[1] for o in outs)
+        nJ = Ds[:4].copy()
+        acc = Ds
+    for c in conns:
+        c.send(None)
+    for pr in procs:
+        pr.join()
+    return acc, wall
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(wl, label: str, per_core: int = 65536, steps: int = 3, check_per: int = 4096):
+    """The oracle as it stands (single-threaded binary64 C) on the host:
+    1 core pinned, and all usable cores as one process per core on disjoint
+    particle subsets (n_CR, J_CR summed across the subsets before each step,
+    so the Hall field is that of all particles).  First, on a small set, the
+    per-core split is checked to give the same integers as one process."""
     from oracle import oracle as O
     O.build(force=not os.path.exists(O.LIB))
-    ns = max(1, wl.N // sample_div)
-    box = O.Box(ndim=wl.box.ndim, n=tuple(wl.box.n), dx=tuple(wl.box.dx), x0=tuple(wl.box.x0),
-                C=wl.box.C, qomc_gas=wl.box.qomc_gas, hall=wl.box.hall,
-                frac_bits=wl.box.frac_bits, max_move_cells=wl.box.max_move_cells)
-    sysO = O.System(box, wl.x[:, :ns].copy(), wl.v[:, :ns].copy(), wl.m[:ns].copy(),
-                    wl.qm[:ns].copy())
-    t0 = time.perf_counter()
-    sysO.step(wl.B, wl.vg, wl.rho, wl.dt, steps)
-    el = time.perf_counter() - t0
-    rate = ns * steps / el
-    log(f"oracle: {ns} particles x {steps} steps in {el:.2f} s -> {rate:.4g} updates/s")
-    return dict(value=rate, unit="particle-updates/s", cores=1, kind="oracle",
-                sample=f"first {ns} of {wl.N} particles of {label} on its full grid, "
-                       f"{steps} steps, single thread, {el:.1f} s")
+    avail = sorted(os.sched_getaffinity(0))
+    P = max(1, min(16, len(avail)))  # a GPU box's CPU share is 16 cores
+    rng = np.random.default_rng(11)
+    # equality of the split with one process on P * check_per particles
+    pick = rng.choice(wl.N, size=min(wl.N, P * check_per), replace=False)
+    one, _ = _oracle_parallel(wl, [pick], 2, None)
+    split, _ = _oracle_parallel(wl, np.array_split(pick, P), 2, None)
+    identical = bool((one == split).all())
+    log(f"oracle split over {P} processes: deposits identical to one process: {identical}")
+    # timing: per_core particles on each core
+    sel = rng.choice(wl.N, size=min(wl.N, P * per_core), replace=False)
+    _, wall1 = _oracle_parallel(wl, [sel[:per_core]], steps, [avail[0]])
+    rate1 = per_core * steps / wall1
+    _, wallP = _oracle_parallel(wl, np.array_split(sel, P), steps, avail[:P])
+    rateP = len(sel) * steps / wallP
+    log(f"oracle: 1 core {rate1:.4g} updates/s, {P} cores {rateP:.4g} updates/s ({cpu_model()})")
+    return dict(value=rateP, unit="particle-updates/s", cores=P, kind="oracle",
+                single_core_value=rate1, cpu_model=cpu_model(),
+                split_deposits_identical_to_one_process=identical,
+                sample=f"{per_core} particles per core drawn from {label} on its full grid, "
+                       f"{steps} steps; one process per core, pinned, n_CR and J_CR summed "
+                       f"over the processes before each step; 1-core leg: {per_core} "
+                       f"particles on one pinned core")
 
 
 # --------------------------------------------------------------------------
@@ -432,6 +579,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="bell3d")
     ap.add_argument("--tile", default="0,0,0")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="fp32: the precision form on the chosen workload (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form and batched-form legs")
@@ -443,20 +592,42 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "shockwall":
+        out = run_shock_wall_form(args.steps, args.warmup)
+        print(json.dumps({"metric": "particle-updates/s (gather+push+deposit)", "value": out["value"],
+                          "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "higher_is_better": True, "dtype": "f64",
+                          "data": "synthetic (seeded; the shock set-up of Sec. 5)",
+                          "config": {"workload": out["workload"]}, "shock_wall": out}), flush=True)
+        return
+    if args.workload == "batch2d":
+        # the batched form alone (profiling runs): steps as one graph launch
+        out = run_batched_form(args.steps)
+        print(json.dumps({"metric": "particle-updates/s (gather+push+deposit)", "value": out["value"],
+                          "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": 0, "higher_is_better": True, "dtype": "f32",
+                          "data": "synthetic (seeded; 256 gyration-test boxes)",
+                          "config": {"workload": out["workload"]}, "batched": out}), flush=True)
+        return
     wl, label = make_workload(args.workload)
     tile = tuple(int(a) for a in args.tile.split(","))
-    g = run_gpu(wl, args.steps, args.warmup, args.calibrate_copy, tile=tile)
+    # the oracle's processes are forked before this process touches the GPU
+    cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
+    prec = 1 if args.precision == "fp32" else 0
+    g = run_gpu(wl, args.steps, args.warmup, args.calibrate_copy, tile=tile, precision=prec)
     N = wl.N
     ms = g["ms"]
     value = N * args.steps / (ms * 1e-3)
     push_ms, push_n = g["push"]
-    alg = algorithmic_bytes(wl.box.ndim, N, g["n_cells"])
+    fsz = 4 if prec else 8
+    alg = algorithmic_bytes(wl.box.ndim, N, g["n_cells"], fsz=fsz, msz=fsz)
     push_avg_s = push_ms * 1e-3 / max(push_n, 1)
     achieved = alg["per_launch"] / push_avg_s / 1e9
     traffic = load_traffic(label, alg["per_launch"])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_push_f64", avg_launch_us=round(push_avg_s * 1e6, 2),
+                    kernel="k_push_f32" if prec else "k_push_f64",
+                    avg_launch_us=round(push_avg_s * 1e6, 2),
                     alg_bytes_per_launch=alg["per_launch"],
                     alg_bytes_per_particle=alg["per_particle"], alg_bytes_per_cell=alg["per_cell"])
     forms = None
@@ -468,10 +639,11 @@ def main():
         forms["subcycled"] = run_subcycled_form(20, 2)
         torch.cuda.empty_cache()
         forms["strip2d"] = run_strip_form(20, 3)
+        torch.cuda.empty_cache()
+        forms["shock_wall"] = run_shock_wall_form(20, 3)
     # (a counter-collection run keeps its one calibration copy alone)
     copy_gbps = None if args.calibrate_copy else measure_copy_gbps()
     log(f"device copy: {copy_gbps} GB/s (read + written)")
-    cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     phases = {k: dict(ms=round(v[0], 3), launches=v[1]) for k, v in g["phases"].items()}
     phases["steps"] = g["breakdown_steps"]
     out = {
@@ -485,11 +657,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if prec else "f64",
         "data": DATA_NOTE.get(args.workload, "synthetic (seeded)"),
         "config": {"workload": label, "cells": g["n_cells"], "particles": N, "ndim": wl.box.ndim,
                    "hall": wl.box.hall, "C": wl.box.C, "dt": wl.dt, "tile": list(tile),
-                   "precision": "fp64"},
+                   "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms_instrumented_pass": phases,

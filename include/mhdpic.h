@@ -69,6 +69,18 @@ enum {
 
 enum { MHDPIC_FP64 = 0, MHDPIC_FP32_MIXED = 1 };
 
+/* Particle boundary of one face of a box (Sec. 5: a conducting wall at x = 0
+ * and an inflow boundary at x = L_x; periodic otherwise).  A particle that
+ * crosses a reflecting face in a half drift is mirrored back (its offset and
+ * that axis's velocity change sign; one landing exactly on the upper face
+ * stays at the largest offset below 1/2 of the last cell); one that crosses
+ * an absorbing face leaves the box (crossed in the first half drift it
+ * deposits nothing, in the second it deposits -dM, -dE_k but no n_CR,
+ * J_CR).  Stencil cells beyond a non-periodic face are their mirror images
+ * inside (cell -1-k is cell k, cell n+k is cell n-1-k), for gathers and
+ * deposits alike. */
+enum { MHDPIC_PERIODIC = 0, MHDPIC_REFLECT = 1, MHDPIC_ABSORB = 2 };
+
 /* One periodic box of the grid (units: the paper's code units, Sec. 5). */
 typedef struct {
     int32_t ndim;           /* 2 or 3; every box of one context has the same ndim */
@@ -84,6 +96,11 @@ typedef struct {
                                (App. A.4); mhdpic_step rejects C*|dt|/dx above it */
     int32_t tile[3];        /* cells per tile per dimension for the LDS-staged kernels;
                                0 = library default.  tile[2] is ignored in 2D */
+    int32_t boundary[3][2]; /* per axis, low and high face: MHDPIC_PERIODIC (both faces or
+                               neither), MHDPIC_REFLECT or MHDPIC_ABSORB; all zero =
+                               periodic.  A non-periodic axis needs at least 2 cells */
+    int64_t capacity;       /* particle slots reserved for this box, for mhdpic_inject;
+                               0 or less than its initial count: the initial count */
 } mhdpic_box;
 
 typedef struct mhdpic_ctx mhdpic_ctx;
@@ -107,6 +124,30 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
                 int32_t precision, const double* x, const double* v, const double* m,
                 const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
                 mhdpic_ctx** out);
+
+/* One call without a context: the particles of mhdpic_init are set up in
+ * `workspace` (at least mhdpic_workspace_size bytes for the same boxes,
+ * counts and precision, 256-byte aligned), advanced n_steps steps of n_sub
+ * particle sub-steps each through fixed fields as mhdpic_step_sub does, and
+ * written back; nothing is kept after the call.  The same results, bit for
+ * bit, as mhdpic_init + mhdpic_step_sub + mhdpic_particles_read +
+ * mhdpic_deposit_read on a new context.
+ *   x, v, m, qm      device inputs as for mhdpic_init
+ *   B, vg, rho, dt   fields and host time steps as for mhdpic_step
+ *   n_steps >= 0, 1 <= n_sub <= 1024
+ *   x_out, v_out     device, [3][N] doubles: final global positions and
+ *                    four-velocities, in the input particle order
+ *   deposits_out     device, [8][cells] int64: n_CR, J_CR at the final
+ *                    positions, then -dM, -dE_k accumulated over the call
+ * The workspace is scratch: its contents are undefined afterwards and it may
+ * be reused as soon as the call returns.  Waits for the stream; device
+ * errors (ENONFINITE, ERANGE) are returned by this call.  Other errors as for
+ * mhdpic_init and mhdpic_step. */
+int mhdpic_advance(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                   int32_t precision, const double* x, const double* v, const double* m,
+                   const double* qm, const double* B, const double* vg, const double* rho,
+                   const double* dt, int32_t n_steps, int32_t n_sub, double* x_out, double* v_out,
+                   int64_t* deposits_out, void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Advances all particles n_steps steps (App. A.2, A.3) through fixed fields.
  * Waits for the stream only when dt differs from the previous call (the new
@@ -196,10 +237,48 @@ int mhdpic_autotune(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_p
 int mhdpic_deposit_read(mhdpic_ctx* ctx, int64_t* out, int32_t reset_accumulated,
                         void* hip_stream);
 
-/* Copies particle states to x, v (device, [3][N] doubles) in the original
- * particle order: global positions x0 + dx*((i + 1/2) + offset) (z = 0 in
- * 2D) and four-velocities.  Does not wait. */
+/* Copies particle states to x, v (device, [3][N] doubles, N the particles
+ * given to mhdpic_init) in the original particle order: global positions
+ * x0 + dx*((i + 1/2) + offset) (z = 0 in 2D) and four-velocities.  Columns
+ * of particles that have left their box (absorbing faces, mhdpic_remove_tagged)
+ * read NaN.  MHDPIC_ESTATE once particles were added (mhdpic_inject): use
+ * mhdpic_particles_read_ids.  Does not wait. */
 int mhdpic_particles_read(mhdpic_ctx* ctx, double* x, double* v, void* hip_stream);
+
+/* Particles in their boxes (Sec. 5 runs add and remove particles): writes
+ * the *n_out current particles, compacted in an unspecified order, to x, v
+ * (device, [3][n_max] doubles, positions and four-velocities as for
+ * mhdpic_particles_read), ids (device, [n_max] int32: the index of a particle
+ * in mhdpic_init's arrays, then numbered on by mhdpic_inject in call order
+ * and array order) and, if not NULL, tags (device, [n_max] doubles: the tags
+ * given to mhdpic_inject, +infinity for particles without one).  Returns
+ * MHDPIC_ENOMEM if more than n_max particles exist (*n_out still holds their
+ * number; the first n_max found are written).  Waits for the stream. */
+int mhdpic_particles_read_ids(mhdpic_ctx* ctx, double* x, double* v, int32_t* ids, double* tags,
+                              int64_t n_max, int64_t* n_out, void* hip_stream);
+
+/* Current particles per box: counts (host, [n_boxes] int64).  Waits. */
+int mhdpic_counts(mhdpic_ctx* ctx, int64_t* counts, void* hip_stream);
+
+/* Adds particles (Sec. 5: CRs injected at the shock front each step): n_new
+ * (host, [n_boxes]) particles per box, box 0's first, from global positions
+ * x and four-velocities v (device, [3][sum n_new] doubles), m, qm (device,
+ * [sum n_new] doubles) and tags (device, [sum n_new] doubles, may be NULL:
+ * +infinity), for instance the injection time.  The new particles join n_CR,
+ * J_CR at once (the next step's cell-centred E sees them); the caller takes
+ * their mass, momentum and energy from the gas (the paper's compensation).
+ * A position must lie inside its box along non-periodic axes (MHDPIC_ERANGE
+ * otherwise, returned after the particles were added).  MHDPIC_ENOMEM if the
+ * context's slots (the sum of the boxes' capacity, or of their initial counts)
+ * cannot hold them.  Waits for the stream. */
+int mhdpic_inject(mhdpic_ctx* ctx, const int64_t* n_new, const double* x, const double* v,
+                  const double* m, const double* qm, const double* tags, void* hip_stream);
+
+/* Removes the particles whose tag is below t_cut once t_now is at least twice
+ * their tag (Sec. 5: particles injected before t_cut are removed at twice
+ * their injection time); their n_CR, J_CR leave the current deposits.  Needs
+ * a context with a capacity (tags).  Waits for the stream. */
+int mhdpic_remove_tagged(mhdpic_ctx* ctx, double t_cut, double t_now, void* hip_stream);
 
 /* Waits for the stream and returns the latched device error (then clears it):
  * MHDPIC_OK, MHDPIC_ENONFINITE, MHDPIC_ERANGE or MHDPIC_ESTATE. */

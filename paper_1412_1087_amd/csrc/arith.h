@@ -125,7 +125,7 @@ namespace mhdpic {
 
 struct Kin32 {
     float u[3];
-    double ek;
+    double g;  // Lorentz factor
 };
 
 __device__ __forceinline__ Kin32 lorentz32(const float v[3], double C, double C2, double iC) {
@@ -133,12 +133,11 @@ __device__ __forceinline__ Kin32 lorentz32(const float v[3], double C, double C2
     double v0 = v[0], v1 = v[1], v2 = v[2];
     double s = dot3(v0, v1, v2, v0, v1, v2);
     double r = __builtin_sqrt(C2 + s);
-    double g = r * iC;
+    k.g = r * iC;
     double ig = C / r;
     k.u[0] = (float)(v0 * ig);
     k.u[1] = (float)(v1 * ig);
     k.u[2] = (float)(v2 * ig);
-    k.ek = s / (g + 1.0);
     return k;
 }
 
@@ -163,7 +162,9 @@ __device__ __forceinline__ void tscf(float d, float w[3]) {
     w[2] = 0.5f * (b * b);
 }
 
-// Policies used by the kernels that exist in both precisions.
+// Policies used by the kernels that exist in both precisions.  Besides the
+// working precision they fix how the corrector's momentum and energy changes
+// (App. A.3) are formed: `Inc` carries what the push hands to `corrector`.
 struct F64Pol {
     using R = double;
     using Part = PartF64;
@@ -171,6 +172,7 @@ struct F64Pol {
         double u[3];
         double ek;
     };
+    struct Inc {};
     __device__ static __forceinline__ K kin(const double v[3], double C, double C2, double iC) {
         Kin k = lorentz(v, C, C2, iC);
         return K{{k.u[0], k.u[1], k.u[2]}, k.ek};
@@ -181,8 +183,18 @@ struct F64Pol {
     __device__ static __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
     __device__ static __forceinline__ void clean(double E[3], const double B[3]) { clean_parallel(E, B); }
     __device__ static __forceinline__ void push(const double v[3], const double E[3], const double B[3],
-                                                double hq, double C, double C2, double vn[3]) {
+                                                double hq, double C, double C2, double vn[3], Inc&) {
         boris(v, E, B, hq, C, C2, vn);
+    }
+    // the canonical sequence: differences of the stored states, E_k from
+    // v^2/(gamma+1) at both ends (Sec. 2.2, eq. parEk)
+    __device__ static __forceinline__ void corrector(const double v[3], const double vn[3],
+                                                     const K& k0, const K& k1, const Inc&,
+                                                     double dv[3], double& dek) {
+        dv[0] = vn[0] - v[0];
+        dv[1] = vn[1] - v[1];
+        dv[2] = vn[2] - v[2];
+        dek = k1.ek - k0.ek;
     }
 };
 
@@ -190,6 +202,11 @@ struct F32Pol {
     using R = float;
     using Part = PartF32;
     using K = Kin32;
+    // Binary64 changes of the kick-rotate-kick, from its own terms (see push)
+    struct Inc {
+        double dv[3];  // v' - v = x + 2 he, x the rotation's change q x t
+        double num;    // |v'|^2 - |v|^2 = 2 he . (2 w + x)
+    };
     __device__ static __forceinline__ K kin(const float v[3], double C, double C2, double iC) {
         return lorentz32(v, C, C2, iC);
     }
@@ -207,9 +224,17 @@ struct F32Pol {
             E[2] = E[2] - f * B[2];
         }
     }
-    // binary32 kick and rotation; 1/gamma of v0 in binary64
+    // binary32 kick and rotation; 1/gamma of v0 in binary64.  The stored
+    // v' is rounded to binary32, so v' - v and E_k(v') - E_k(v) of the stored
+    // states would carry that rounding, about 1e-7 |v| and 1e-7 |v|^2, however
+    // small the change itself.  The changes are therefore also formed in
+    // binary64 from the step's own terms: v' - v = x + 2 he exactly, with x
+    // = q x t the rotation's change (a product of binary32 numbers, exact in
+    // binary64, minus another), and, because the rotation keeps |w + x| = |w|,
+    // |v'|^2 - |v|^2 = 2 he . (2 w + x).
     __device__ static __forceinline__ void push(const float v[3], const float E[3], const float B[3],
-                                                double hqd, double C, double C2, float vn[3]) {
+                                                double hqd, double C, double C2, float vn[3],
+                                                Inc& inc) {
         const float hq = (float)hqd;
         float he0 = hq * E[0], he1 = hq * E[1], he2 = hq * E[2];
         float w0 = v[0] + he0, w1 = v[1] + he1, w2 = v[2] + he2;
@@ -226,6 +251,23 @@ struct F32Pol {
         vn[0] = (w0 + (q1 * t2 - q2 * t1)) + he0;
         vn[1] = (w1 + (q2 * t0 - q0 * t2)) + he1;
         vn[2] = (w2 + (q0 * t1 - q1 * t0)) + he2;
+        const double x0 = (double)q1 * (double)t2 - (double)q2 * (double)t1;
+        const double x1 = (double)q2 * (double)t0 - (double)q0 * (double)t2;
+        const double x2 = (double)q0 * (double)t1 - (double)q1 * (double)t0;
+        const double h0 = he0, h1 = he1, h2 = he2;
+        inc.dv[0] = x0 + 2.0 * h0;
+        inc.dv[1] = x1 + 2.0 * h1;
+        inc.dv[2] = x2 + 2.0 * h2;
+        inc.num = 2.0 * dot3(h0, h1, h2, 2.0 * wd0 + x0, 2.0 * wd1 + x1, 2.0 * wd2 + x2);
+    }
+    // E_k(v') - E_k(v) = (|v'|^2 - |v|^2) / (gamma' + gamma)  (Sec. 2.2, eq. parEk)
+    __device__ static __forceinline__ void corrector(const float*, const float*, const K& k0,
+                                                     const K& k1, const Inc& inc, double dv[3],
+                                                     double& dek) {
+        dv[0] = inc.dv[0];
+        dv[1] = inc.dv[1];
+        dv[2] = inc.dv[2];
+        dek = inc.num / (k1.g + k0.g);
     }
 };
 

@@ -16,32 +16,15 @@
 
 namespace mhdpic {
 
-// Cell of the half step x^(n+1/2) = x^(n) + u dt/2, with exactly the
-// operations of the step kernel of the precision form.
-template <class Pol, int NDIM>
-__device__ __forceinline__ void half_step_cell(const typename Pol::Part& P, int j, const BoxDev& bx,
-                                               int i[3], int& cls) {
-    using R = typename Pol::R;
-    unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-    R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
-    typename Pol::K kn = Pol::kin(v, bx.C, bx.C2, bx.iC);
-    int s[3] = {0, 0, 0};
-    for (int d = 0; d < NDIM; ++d) {
-        R dl = P.d[d][j];
-        const R h = Pol::hdx(bx.hdx[d]);
-        i[d] = wrap_shift(i[d], Pol::drift(dl, kn.u[d], h), bx.n[d]);
-        s[d] = Pol::drift(dl, kn.u[d], h);  // predicted second half drift
-    }
-    cls = shift_class<NDIM>(s[0], s[1], s[2]);
-}
-
-// Code words for this call's dt; the push computes them for the later steps
-// of the call.
+// Code words for this call's dt (the push computes them for the later steps
+// of the call): next_code of each particle's stored state, with the
+// operations of the step's first half drift.
 template <class Pol, int NDIM>
 __global__ void __launch_bounds__(256)
 k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __restrict__ cnt,
               const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items,
               const BoxDev* __restrict__ boxes, int3 T, uint32_t* err) {
+    using R = typename Pol::R;
     constexpr int K = Codes<NDIM>::K;
     __shared__ uint32_t s_cnt[K];
     uint32_t item;
@@ -52,14 +35,18 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     for (int c = threadIdx.x; c < K; c += blockDim.x) s_cnt[c] = 0;
     __syncthreads();
+    const R hx = Pol::hdx(bx.hdx[0]), hy = Pol::hdx(bx.hdx[1]), hz = Pol::hdx(bx.hdx[2]);
     uint32_t errbits = 0;
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
-        int i[3], cls;
-        half_step_cell<Pol, NDIM>(P, j, bx, i, cls);
-        int res;
-        const int k = move_code<NDIM>(bx, T, tx, ty, tz, i, errbits, res);
-        code[j] = pack_code(k, res, cls);
-        atomicAdd(&s_cnt[k], 1u);
+        const uint32_t cell = P.cell[j];
+        int i[3];
+        unpack_cell<NDIM>(cell, i[0], i[1], i[2]);
+        R dl[3] = {P.d[0][j], P.d[1][j], NDIM == 3 ? P.d[2][j] : R(0)};
+        R v[3] = {P.v[0][j], P.v[1][j], P.v[2][j]};
+        typename Pol::K kn = Pol::kin(v, bx.C, bx.C2, bx.iC);
+        const int k = next_code<Pol, NDIM>(bx, T, tx, ty, tz, i, dl, v, kn.u, hx, hy, hz,
+                                           cell == kDeadCell, errbits, code[j]);
+        if (k != Codes<NDIM>::GONE) atomicAdd(&s_cnt[k], 1u);
     }
     if (errbits) latch(err, errbits);
     __syncthreads();
@@ -232,7 +219,8 @@ struct MoveMap {
     const uint16_t* from;  // local slot -> source index in the item
     const uint8_t* grp;    // local slot -> group
     const uint32_t* goff;  // group -> destination of local slot 0
-    int begin, n;
+    int begin, n;          // first source slot, source particles
+    int nd;                // destination slots (the particles that stay in a box)
 };
 
 template <int BLOCK, typename T>
@@ -270,7 +258,7 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int L = threadIdx.x + u * BLOCK;
-        if (L < mm.n) dst[mm.goff[mm.grp[L]] + (uint32_t)L] = st[mm.from[L]];
+        if (L < mm.nd) dst[mm.goff[mm.grp[L]] + (uint32_t)L] = st[mm.from[L]];
     }
     __syncthreads();
 }
@@ -289,7 +277,9 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
 // Pass 1 ranks every particle within its (group, residue) by an LDS counter;
 // pass 2 turns the ranks into an LDS map from destination to source, and the
 // particles are moved one array at a time through LDS (MoveMap, move_step).
-template <int NDIM, typename PS, int BLOCK>
+// TAGGED: the context carries particle tags (binary64), moved last; the
+// staging buffer is then 8 bytes per particle in both precisions.
+template <int NDIM, typename PS, int BLOCK, bool TAGGED>
 __global__ void __launch_bounds__(BLOCK)
 k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
                     const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
@@ -299,10 +289,11 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     constexpr int NG = NCL + K;   // groups: stay classes, then moving codes
     constexpr int RS = kResidues;
     __shared__ uint32_t s_n[NG * RS];
-    __shared__ uint32_t s_off[NG], s_lbase[NG];
+    __shared__ uint32_t s_off[NG], s_lbase[NG], s_nd;
     __shared__ uint16_t s_src[kItemParticles];
     __shared__ uint8_t s_grp[kItemParticles];
-    __shared__ typename PS::R s_stage[kItemParticles];
+    using SR = typename std::conditional<TAGGED, double, typename PS::R>::type;
+    __shared__ SR s_stage[kItemParticles];
     uint32_t* s_key = reinterpret_cast<uint32_t*>(s_stage);  // ranks, until the moves
     uint32_t item;
     if (!item_of_block(n_items, item)) return;
@@ -311,7 +302,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     using R = typename PS::R;
     constexpr int NR = NDIM + 5;  // offsets, four-velocity, m, q/m
     constexpr int U = kItemParticles / BLOCK;
-    const MoveMap mm{s_src, s_grp, s_off, w.begin, w.end - w.begin};
+    MoveMap mm{s_src, s_grp, s_off, w.begin, w.end - w.begin, 0};
     const R* rsrc[NR];
     R* rdst[NR];
 #pragma unroll
@@ -348,6 +339,10 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         const int L = threadIdx.x + u * BLOCK;
         if (L < mm.n) {
             const int k = code_dir(cr[u]), b = code_residue(cr[u]);
+            if (k == Codes<NDIM>::GONE) {  // left the box: no destination slot
+                s_key[L] = 0xFFFFFFFFu;
+                continue;
+            }
             const int g = k == STAY ? code_class(cr[u]) : NCL + k;
             const uint32_t r = atomicAdd(&s_n[g * RS + b], 1u);
             s_key[L] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16);
@@ -370,6 +365,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
             if (g >= o) x += y;
         }
         const uint32_t lb = x - t;  // slots of the groups before g
+        if (g == 63) s_nd = x;      // all groups: the particles that stay
         if (g < NG) {
             const uint32_t base = g < NCL ? off[(size_t)item * K + STAY] + lb
                                           : off[(size_t)item * K + (g - NCL)];
@@ -378,8 +374,10 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         }
     }
     __syncthreads();
+    mm.nd = (int)s_nd;
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
         const uint32_t key = s_key[j - w.begin];
+        if (key == 0xFFFFFFFFu) continue;
         const uint32_t r = key & 4095u;
         const int b = (int)((key >> 12) & 15u), g = (int)(key >> 16);
         const uint32_t* nk = s_n + g * RS;
@@ -401,29 +399,44 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         move_step<BLOCK>(rbuf[q & 1], rdst[q], s_stage, rbuf[q & 1], rsrc[q + 2], mm);
     move_step<BLOCK>(rbuf[(NR - 2) & 1], rdst[NR - 2], s_stage, rpid, A.pid, mm);
     move_step<BLOCK>(rbuf[(NR - 1) & 1], rdst[NR - 1], s_stage, rcell, (const uint32_t*)nullptr, mm);
-    move_step<BLOCK>(rpid, Bo.pid, s_stage, rcell, (const uint32_t*)nullptr, mm);
+    if (TAGGED) {
+        ItemRegs<BLOCK, double> rtag;
+        move_step<BLOCK>(rpid, Bo.pid, s_stage, rtag, (const double*)A.tag, mm);
+        move_step<BLOCK>(rtag, Bo.tag, s_stage, rcell, (const uint32_t*)nullptr, mm);
+    } else {
+        move_step<BLOCK>(rpid, Bo.pid, s_stage, rcell, (const uint32_t*)nullptr, mm);
+    }
 }
 
-// Initial sort: key = tile of the particle's current cell (any tile), with
-// global counters; used once per context.
+// Sort key of slot j: the tile of the particle's current cell (any tile of
+// its box), or kNoTile for a particle that has left its box.
+template <int NDIM, typename PS>
+__device__ __forceinline__ uint32_t sort_key(const PS& P, int64_t j, const SlotBoxes& sb,
+                                             const BoxDev* boxes, int3 T) {
+    const uint32_t c = P.cell[j];
+    if (c == kDeadCell) return kNoTile;
+    const BoxDev& bx = boxes[sb.box(j)];
+    int i[3];
+    unpack_cell<NDIM>(c, i[0], i[1], i[2]);
+    return tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+}
+
+// Sort by tile (first sort of a context, and re-sorts after particles are
+// added or removed), with global counters.
 template <int NDIM, typename PS>
 __global__ void k_key_cell(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                           const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
-                           int nb, int64_t N, int3 T) {
+                           const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N, int3 T) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = j < N;
-    uint32_t k = 0;
-    if (act) {
-        const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-        int i[3];
-        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-        k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+    uint32_t k = kNoTile;
+    if (j < N) {
+        k = sort_key<NDIM>(P, j, sb, boxes, T);
         key[j] = k;
     }
-    wave_claim(count, k, act);
+    const bool act = k != kNoTile;
+    wave_claim(count, act ? k : 0u, act);
 }
 
-// Initial sort with per-block tile histograms in LDS, for a tile count that
+// The same sort with per-block tile histograms in LDS, for a tile count that
 // fits (NT <= kSortLdsTiles): each block takes kSortChunk consecutive
 // particles, counts their tiles in LDS and adds each non-zero count to the
 // global counter once, so a counter sees one atomic per block however the
@@ -434,8 +447,7 @@ constexpr int kSortLdsTiles = 32768;  // 128 KB of LDS histogram at most
 template <int NDIM, typename PS>
 __global__ void __launch_bounds__(256)
 k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off, int nb,
-                int64_t N, int3 T, int NT) {
+                const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N, int3 T, int NT) {
     extern __shared__ uint32_t s_h[];
     constexpr int U = kSortChunk / 256;
     for (int t = threadIdx.x; t < NT; t += 256) s_h[t] = 0;
@@ -445,12 +457,9 @@ k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
     for (int u = 0; u < U; ++u) {
         const int64_t j = j0 + threadIdx.x + u * 256;
         if (j < N) {
-            const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-            int i[3];
-            unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
-            const uint32_t k = tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+            const uint32_t k = sort_key<NDIM>(P, j, sb, boxes, T);
             key[j] = k;
-            atomicAdd(&s_h[k], 1u);
+            if (k != kNoTile) atomicAdd(&s_h[k], 1u);
         }
     }
     __syncthreads();
@@ -460,7 +469,8 @@ k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
 
 // Moves every particle to its slot in the tile-sorted order: the same chunks
 // and LDS histograms as k_key_count_lds; each block claims one range per
-// tile from the global cursor and hands out its slots in LDS.
+// tile from the global cursor and hands out its slots in LDS.  Particles
+// keyed kNoTile are dropped.
 template <int NDIM, typename PS>
 __global__ void __launch_bounds__(256)
 k_scatter_lds(PS A, PS Bo, const uint32_t* __restrict__ key, uint32_t* __restrict__ cursor,
@@ -474,13 +484,10 @@ k_scatter_lds(PS A, PS Bo, const uint32_t* __restrict__ key, uint32_t* __restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t j = j0 + threadIdx.x + u * 256;
-        k[u] = j < N ? key[j] : 0u;
+        k[u] = j < N ? key[j] : kNoTile;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = j0 + threadIdx.x + u * 256;
-        r[u] = j < N ? atomicAdd(&s_h[k[u]], 1u) : 0u;
-    }
+    for (int u = 0; u < U; ++u) r[u] = k[u] != kNoTile ? atomicAdd(&s_h[k[u]], 1u) : 0u;
     __syncthreads();
     for (int t = threadIdx.x; t < NT; t += 256) {
         const uint32_t c = s_h[t];
@@ -490,15 +497,7 @@ k_scatter_lds(PS A, PS Bo, const uint32_t* __restrict__ key, uint32_t* __restric
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t j = j0 + threadIdx.x + u * 256;
-        if (j < N) {
-            const uint32_t sl = s_h[k[u]] + r[u];
-            Bo.cell[sl] = A.cell[j];
-            for (int d = 0; d < NDIM; ++d) Bo.d[d][sl] = A.d[d][j];
-            for (int d = 0; d < 3; ++d) Bo.v[d][sl] = A.v[d][j];
-            Bo.m[sl] = A.m[j];
-            Bo.qm[sl] = A.qm[j];
-            Bo.pid[sl] = A.pid[j];
-        }
+        if (k[u] != kNoTile) copy_particle<NDIM>(A, Bo, j, s_h[k[u]] + r[u]);
     }
 }
 

@@ -4,7 +4,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mhdpic {
+
+// Particle boundary of a face.
+enum : int32_t { FACE_PERIODIC = 0, FACE_REFLECT = 1, FACE_ABSORB = 2 };
+
+// Packed cell of a particle that has left its box through an absorbing face;
+// it stays in its slot until the next binning drops it.
+constexpr uint32_t kDeadCell = 0xFFFFFFFFu;
 
 // Error bits latched by kernels in the device error word.
 enum : uint32_t {
@@ -30,6 +39,7 @@ struct BoxDev {
     int32_t tile_off;  // global index of this box's first tile
     int32_t hall;
     int32_t small_last[3];  // 1: the last tile starts at n-2 (no 1-cell tiles)
+    int32_t face[3][2];     // per axis, low/high: FACE_PERIODIC, FACE_REFLECT, FACE_ABSORB
     int32_t pad0;
     int64_t cell_off;  // global index of this box's first cell
     int64_t part_off;  // first particle slot of this box
@@ -47,6 +57,11 @@ struct BoxDev {
 // Particle store, structure of arrays.  cell holds the packed cell indices
 // (2D: ix | iy<<16; 3D: ix | iy<<11 | iz<<22); d holds the offsets from the
 // cell centre in cell units; v the spatial four-velocity gamma*u.
+// pid is the particle's id (its index in the initial arrays, then numbered
+// on from there for added particles); tag, present only in contexts with a
+// particle capacity for additions, is the caller's tag of each particle (the
+// injection time of Sec. 5), moved with the particle and never read by the
+// step.
 struct PartF64 {
     using R = double;
     uint32_t* cell;
@@ -55,9 +70,11 @@ struct PartF64 {
     double* m;
     double* qm;
     int32_t* pid;
+    double* tag;
 };
 
-// Precision form: every per-particle value in single precision.
+// Precision form: every per-particle value in single precision (the tag
+// stays binary64).
 struct PartF32 {
     using R = float;
     uint32_t* cell;
@@ -66,6 +83,7 @@ struct PartF32 {
     float* m;
     float* qm;
     int32_t* pid;
+    double* tag;
 };
 
 struct WorkItem {

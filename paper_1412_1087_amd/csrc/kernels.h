@@ -49,6 +49,10 @@ __device__ __forceinline__ int pmod(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Largest offset below 1/2 (a particle mirrored onto the upper face).
+__device__ __forceinline__ double below_half(double) { return 0x1.fffffffffffffp-2; }
+__device__ __forceinline__ float below_half(float) { return 0x1.fffffep-2f; }
+
 // ---------------------------------------------------------------------------
 // fills and copies
 // ---------------------------------------------------------------------------
@@ -75,58 +79,163 @@ __global__ void k_copy_i64(int64_t* __restrict__ dst, const int64_t* __restrict_
 // initialisation: global positions -> (cell, offset); n_CR, J_CR deposit
 // ---------------------------------------------------------------------------
 
+// Tables derived from the box records: first particle and first cell of each
+// box (with the totals at index nb), and the box of every tile.
+__global__ void k_box_tables(const BoxDev* __restrict__ boxes, int nb, int64_t* __restrict__ part_off,
+                             int64_t* __restrict__ cell_off, int32_t* __restrict__ tile_box, int NT) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) {
+        part_off[i] = boxes[i].part_off;
+        cell_off[i] = boxes[i].cell_off;
+    } else if (i == nb) {
+        const BoxDev& l = boxes[nb - 1];
+        part_off[nb] = l.part_off + l.part_n;
+        cell_off[nb] = l.cell_off + (int64_t)l.n[0] * l.n[1] * l.n[2];
+    }
+    if (i < NT) {
+        int lo = 0, hi = nb - 1;  // last box whose first tile is <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boxes[mid].tile_off <= i) lo = mid; else hi = mid - 1;
+        }
+        tile_box[i] = lo;
+    }
+}
+
+// Converts new particles j = 0 .. N-1 (global positions x, four-velocities
+// v, [3][N]; m, qm, optional tags, [N]) of the boxes new_off[] describes
+// into slots slot0 + j of P, with ids pid0 + j.  Without tags a particle's
+// tag is +infinity (no removal by tag ever takes it).
 template <int NDIM, typename PS, typename T>
 __global__ void k_init_convert(PS P, const double* __restrict__ x, const double* __restrict__ v,
                                const double* __restrict__ m, const double* __restrict__ qm,
-                               const BoxDev* __restrict__ boxes, const int64_t* __restrict__ part_off,
-                               int nb, int64_t N, uint32_t* err) {
+                               const double* __restrict__ tag, const BoxDev* __restrict__ boxes,
+                               const int64_t* __restrict__ new_off, int nb, int64_t N,
+                               int64_t slot0, int32_t pid0, uint32_t* err) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    int b = find_box(part_off, nb, j);
+    int b = find_box(new_off, nb, j);
     const BoxDev& bx = boxes[b];
+    const int64_t sl = slot0 + j;
     int ic[3] = {0, 0, 0};
     bool bad = false, far = false;
     for (int d = 0; d < NDIM; ++d) {
         double s = (x[d * N + j] - bx.x0[d]) / bx.dx[d];
         double fl = floor(s);
         if (!isfinite(s)) bad = true;
-        // the cell count from x0 must fit a 32-bit int
+        // the cell count from x0 must fit a 32-bit int; on a non-periodic
+        // axis the position must lie inside the box
         else if (!(fl >= -2147483648.0 && fl < 2147483648.0)) far = true;
+        else if (bx.face[d][0] != FACE_PERIODIC && !(fl >= 0.0 && fl < (double)bx.n[d])) far = true;
         double off = (s - fl) - 0.5;
         ic[d] = (bad || far) ? 0 : pmod((int)(long long)fl, bx.n[d]);
         T o = (T)off;
         if (o >= (T)0.5) {  // binary32 rounding can reach the upper edge
-            o = o - (T)1;
-            ic[d] = wrap_shift(ic[d], 1, bx.n[d]);
+            if (bx.face[d][0] != FACE_PERIODIC && ic[d] == bx.n[d] - 1) {
+                o = below_half(T(0));
+            } else {
+                o = o - (T)1;
+                ic[d] = wrap_shift(ic[d], 1, bx.n[d]);
+            }
         }
-        P.d[d][j] = o;
+        P.d[d][sl] = o;
     }
     for (int d = 0; d < 3; ++d) {
         double vd = v[d * N + j];
         if (!isfinite(vd)) bad = true;
-        P.v[d][j] = (T)vd;
+        P.v[d][sl] = (T)vd;
     }
     if (!isfinite(m[j]) || !isfinite(qm[j])) bad = true;
     if (bad) latch(err, ERRBIT_NONFINITE);
     if (far) latch(err, ERRBIT_RANGE);
-    P.cell[j] = pack_cell<NDIM>(ic[0], ic[1], ic[2]);
-    P.m[j] = m[j];
-    P.qm[j] = qm[j];
-    P.pid[j] = (int32_t)j;
+    P.cell[sl] = pack_cell<NDIM>(ic[0], ic[1], ic[2]);
+    P.m[sl] = m[j];
+    P.qm[sl] = qm[j];
+    P.pid[sl] = pid0 + (int32_t)j;
+    if (P.tag) P.tag[sl] = tag ? tag[j] : (double)INFINITY;
+}
+
+// Marks for removal the particles whose tag is below t_cut once t_now has
+// reached twice their tag (Sec. 5: particles injected before t_cut are
+// removed at twice their injection time).  Slots [0, start[NT]).
+template <typename PS>
+__global__ void k_mark_tagged(PS P, const uint32_t* __restrict__ start, int NT, int64_t cap,
+                              double t_cut, double t_now) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cap || j >= (int64_t)start[NT]) return;
+    if (P.cell[j] == kDeadCell) return;
+    const double t = P.tag[j];
+    if (t < t_cut && 2.0 * t <= t_now) P.cell[j] = kDeadCell;
 }
 
 // ---------------------------------------------------------------------------
 // binning by tile of the half-step cell x^(n+1/2)
 // ---------------------------------------------------------------------------
 
-// Global index of cell (x, y, z) of a periodic box; coordinates may lie
-// outside [0, n) and are wrapped.
+// Cell index along axis d of a coordinate that may lie beyond the box (by at
+// most two cells past a non-periodic face): wrapped on a periodic axis,
+// mirrored at a non-periodic face (cell -1-k is cell k, cell n+k is n-1-k).
+__device__ __forceinline__ int map_index(const BoxDev& bx, int d, int i) {
+    const int n = bx.n[d];
+    if (bx.face[d][0] == FACE_PERIODIC) return pmod(i, n);
+    return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+}
+
+// Global index of cell (x, y, z) of a box; coordinates may lie outside
+// [0, n) and are wrapped or mirrored (map_index).
 template <int NDIM>
 __device__ __forceinline__ int64_t global_cell(const BoxDev& bx, int x, int y, int z) {
-    x = pmod(x, bx.n[0]);
-    y = pmod(y, bx.n[1]);
-    z = NDIM == 3 ? pmod(z, bx.n[2]) : 0;
+    x = map_index(bx, 0, x);
+    y = map_index(bx, 1, y);
+    z = NDIM == 3 ? map_index(bx, 2, z) : 0;
     return bx.cell_off + ((int64_t)z * bx.n[1] + y) * bx.n[0] + x;
+}
+
+// Shift value of half_drift for a particle that left through an absorbing face.
+constexpr int kGone = 8;
+
+// After a half drift has moved the cell index along axis d by one cell at
+// most (i is then -1 .. n): wraps it on a periodic axis; at a reflecting face
+// mirrors the position back (offset, the axis's four-velocity v and
+// three-velocity u negated); at an absorbing face returns true (the particle
+// leaves the box).  From cell 0 the offset in cell -1 is above -1/2, so its
+// negation stays below 1/2; at the upper face it can be exactly -1/2.
+template <typename R>
+__device__ __forceinline__ bool cross_face(const BoxDev& bx, int d, int& i, R& dl, R& v, R& u) {
+    const int n = bx.n[d];
+    if (i >= 0 && i < n) return false;
+    if (bx.face[d][0] == FACE_PERIODIC) {
+        i = i < 0 ? i + n : i - n;
+        return false;
+    }
+    const int side = i < 0 ? 0 : 1;
+    if (bx.face[d][side] == FACE_ABSORB) return true;
+    dl = -dl;
+    v = -v;
+    u = -u;
+    if (side == 0) {
+        i = 0;
+    } else {
+        i = n - 1;
+        if (dl >= R(0.5)) dl = below_half(R(0));
+    }
+    return false;
+}
+
+// One half drift along axis d (App. A.2: x += u dt/2) of a particle in cell i
+// at offset dl, then the face it may have crossed.  Returns the cell shift as
+// the tile's LDS boxes see it (-1, 0, +1; a mirrored particle is back in its
+// own cell, a wrapped one moved by one cell across the periodic seam), or
+// kGone if the particle left through an absorbing face.
+template <class Pol, typename R>
+__device__ __forceinline__ int half_drift(const BoxDev& bx, int d, int& i, R& dl, R& v, R& u, R h) {
+    const int s = Pol::drift(dl, u, h);
+    if (s == 0) return 0;
+    i += s;
+    if (i >= 0 && i < bx.n[d]) return s;
+    const bool periodic = bx.face[d][0] == FACE_PERIODIC;
+    if (cross_face(bx, d, i, dl, v, u)) return kGone;
+    return periodic ? s : 0;
 }
 
 // Tiles along a dimension start at multiples of T, except that when n % T == 1
@@ -152,6 +261,32 @@ __device__ __forceinline__ uint32_t tile_of(const BoxDev& bx, const int3 T, int 
     int tz = NDIM == 3 ? tile_index(bx, 2, iz, T.z) : 0;
     return (uint32_t)(bx.tile_off + (tz * bx.nt[1] + ty) * bx.nt[0] + tx);
 }
+
+// Key of a particle that a sort drops (it has left its box).
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// Box of slot j of a sort's source buffer.  Slots below n_old hold particles
+// already grouped by tile (start[t] is tile t's first slot, tile_box[t] its
+// box); slots from n_old on hold new particles, box by box as new_off[]
+// says.  For the first sort of a context n_old is 0 and new_off holds the
+// per-box particle offsets.
+struct SlotBoxes {
+    const uint32_t* start;
+    const int32_t* tile_box;
+    int NT;
+    int64_t n_old;
+    const int64_t* new_off;
+    int nb;
+    __device__ __forceinline__ int box(int64_t j) const {
+        if (j >= n_old) return find_box(new_off, nb, j - n_old);
+        int lo = 0, hi = NT - 1;  // last tile whose first slot is <= j
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int64_t)start[mid] <= j) lo = mid; else hi = mid - 1;
+        }
+        return tile_box[lo];
+    }
+};
 
 // Exclusive scan of tile counts and the work list: each tile's particles are
 // split into items of at most P particles.  One block of 1024 threads.
@@ -205,21 +340,29 @@ k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
     }
 }
 
-// Moves every particle to its slot in the tile-sorted order.
+// Copies particle j of A to slot s of Bo (every array).
 template <int NDIM, typename PS>
-__global__ void k_scatter(PS A, PS Bo, const uint32_t* __restrict__ key,
-                          uint32_t* __restrict__ cursor, int64_t N) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = j < N;
-    uint32_t k = act ? key[j] : 0u;
-    uint32_t s = wave_claim(cursor, k, act);
-    if (!act) return;
+__device__ __forceinline__ void copy_particle(const PS& A, const PS& Bo, int64_t j, int64_t s) {
     Bo.cell[s] = A.cell[j];
     for (int d = 0; d < NDIM; ++d) Bo.d[d][s] = A.d[d][j];
     for (int d = 0; d < 3; ++d) Bo.v[d][s] = A.v[d][j];
     Bo.m[s] = A.m[j];
     Bo.qm[s] = A.qm[j];
     Bo.pid[s] = A.pid[j];
+    if (A.tag) Bo.tag[s] = A.tag[j];
+}
+
+// Moves every particle to its slot in the tile-sorted order (dropping those
+// keyed kNoTile).
+template <int NDIM, typename PS>
+__global__ void k_scatter(PS A, PS Bo, const uint32_t* __restrict__ key,
+                          uint32_t* __restrict__ cursor, int64_t N) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t k = j < N ? key[j] : kNoTile;
+    bool act = k != kNoTile;
+    uint32_t s = wave_claim(cursor, act ? k : 0u, act);
+    if (!act) return;
+    copy_particle<NDIM>(A, Bo, j, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,6 +373,7 @@ template <int NDIM>
 struct Codes {
     static constexpr int K = NDIM == 3 ? 27 : 9;
     static constexpr int STAY = NDIM == 3 ? 13 : 4;
+    static constexpr int GONE = 31;  // leaves the box: dropped by the binning
 };
 
 // Per-dimension code of a move from tile coordinate a to b on a ring of n
@@ -299,6 +443,36 @@ __device__ __forceinline__ int code_class(uint32_t c) { return (int)(c >> 9); }
 template <int NDIM>
 __device__ __forceinline__ int shift_class(int s0, int s1, int s2) {
     return NDIM == 3 ? ((s2 + 1) * 3 + (s1 + 1)) * 3 + (s0 + 1) : (s1 + 1) * 3 + (s0 + 1);
+}
+
+// Code word of a particle at cell i, offset dl, with four-velocity v and
+// three-velocity u, for the next binning: the operations of the next step's
+// first half drift (faces included) give its half-step cell, whose tile
+// (relative to the item's tile tx, ty, tz) and bank residue go into the code,
+// with the class of the predicted second-drift shift.  A particle that has
+// left (gone) or that this drift takes through an absorbing face gets the
+// gone code.  Returns the direction code.
+template <class Pol, int NDIM, typename R>
+__device__ __forceinline__ int next_code(const BoxDev& bx, int3 T, int tx, int ty, int tz,
+                                         const int i[3], const R dl[3], const R v[3], const R u[3],
+                                         R hx, R hy, R hz, bool gone, uint32_t& errbits,
+                                         uint16_t& code) {
+    int ni[3] = {i[0], i[1], i[2]};
+    R e[3] = {dl[0], dl[1], dl[2]}, w[3] = {v[0], v[1], v[2]}, q[3] = {u[0], u[1], u[2]};
+    if (!gone) gone = half_drift<Pol>(bx, 0, ni[0], e[0], w[0], q[0], hx) == kGone;
+    if (!gone) gone = half_drift<Pol>(bx, 1, ni[1], e[1], w[1], q[1], hy) == kGone;
+    if (NDIM == 3 && !gone) gone = half_drift<Pol>(bx, 2, ni[2], e[2], w[2], q[2], hz) == kGone;
+    if (gone) {
+        code = pack_code(Codes<NDIM>::GONE, 0, 0);
+        return Codes<NDIM>::GONE;
+    }
+    int res;
+    const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits, res);
+    // predicted shift of the predictor deposit after that drift (velocity as now)
+    const int p0 = Pol::drift(e[0], q[0], hx), p1 = Pol::drift(e[1], q[1], hy);
+    const int p2 = NDIM == 3 ? Pol::drift(e[2], q[2], hz) : 0;
+    code = pack_code(k, res, shift_class<NDIM>(p0, p1, p2));
+    return k;
 }
 
 __device__ __forceinline__ bool item_of_block(const uint32_t* n_items, uint32_t& item) {
@@ -425,22 +599,79 @@ __global__ void k_feedback(double* __restrict__ out, const double* __restrict__ 
 // read-out in the original particle order
 // ---------------------------------------------------------------------------
 
+// Global position of slot j: x0 + dx((i + 1/2) + d) per axis (z = 0 in 2D).
 template <int NDIM, typename PS>
-__global__ void k_read_particles(PS P, double* __restrict__ x, double* __restrict__ v,
-                                 const BoxDev* __restrict__ boxes,
-                                 const int64_t* __restrict__ part_off, int nb, int64_t N) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const BoxDev& bx = boxes[find_box(part_off, nb, j)];
-    int64_t p = P.pid[j];
+__device__ __forceinline__ void slot_position(const PS& P, const BoxDev& bx, int64_t j, double x[3]) {
     int i[3];
     unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+    for (int d = 0; d < 3; ++d)
+        x[d] = d < NDIM ? bx.x0[d] + bx.dx[d] * (((double)i[d] + 0.5) + (double)P.d[d][j]) : 0.0;
+}
+
+// Particles in the order of their ids: slot j goes to column pid of the
+// [3][N] outputs (N: the ids given at initialisation).  Slots [0, start[NT]);
+// a particle that has left its box is skipped (its columns keep what the
+// caller filled them with).
+template <int NDIM, typename PS>
+__global__ void k_read_particles(PS P, double* __restrict__ x, double* __restrict__ v,
+                                 const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t cap,
+                                 int64_t N) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cap || j >= (int64_t)sb.start[sb.NT]) return;
+    if (P.cell[j] == kDeadCell) return;
+    const BoxDev& bx = boxes[sb.box(j)];
+    const int64_t p = P.pid[j];
+    double xx[3];
+    slot_position<NDIM>(P, bx, j, xx);
     for (int d = 0; d < 3; ++d) {
-        double xd = 0.0;
-        if (d < NDIM) xd = bx.x0[d] + bx.dx[d] * (((double)i[d] + 0.5) + (double)P.d[d][j]);
-        x[d * N + p] = xd;
+        x[d * N + p] = xx[d];
         v[d * N + p] = (double)P.v[d][j];
     }
+}
+
+// The particles in the boxes, compacted: each live slot takes the next
+// output column from *n_out (one atomic per wave); [3][n_max] outputs,
+// columns beyond n_max are not written (*n_out still counts them).
+template <int NDIM, typename PS>
+__global__ void k_read_ids(PS P, double* __restrict__ x, double* __restrict__ v,
+                           int32_t* __restrict__ ids, double* __restrict__ tags,
+                           const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t cap,
+                           uint32_t* __restrict__ n_out, int64_t n_max) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = j < cap && j < (int64_t)sb.start[sb.NT] && P.cell[j] != kDeadCell;
+    const uint64_t mask = __ballot(live);
+    uint32_t base = 0;
+    const int lane = lane_id();
+    const int leader = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+    if (mask && lane == leader) base = atomicAdd(n_out, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (!live) return;
+    const int64_t o = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (o >= n_max) return;
+    const BoxDev& bx = boxes[sb.box(j)];
+    double xx[3];
+    slot_position<NDIM>(P, bx, j, xx);
+    for (int d = 0; d < 3; ++d) {
+        x[d * n_max + o] = xx[d];
+        v[d * n_max + o] = (double)P.v[d][j];
+    }
+    ids[o] = P.pid[j];
+    if (tags) tags[o] = P.tag ? P.tag[j] : (double)INFINITY;
+}
+
+// Live particles per box (counts[b], int64, zeroed by the caller).
+template <typename PS>
+__global__ void k_box_counts(PS P, SlotBoxes sb, int64_t cap, unsigned long long* __restrict__ counts) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cap || j >= (int64_t)sb.start[sb.NT]) return;
+    if (P.cell[j] == kDeadCell) return;
+    atomicAdd(&counts[sb.box(j)], 1ull);
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double val) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = val;
 }
 
 // ---------------------------------------------------------------------------

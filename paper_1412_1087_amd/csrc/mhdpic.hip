@@ -13,7 +13,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -27,18 +26,24 @@ using namespace mhdpic;
 
 namespace {
 
-thread_local std::string g_last_error;
+// Message of the last failure on this thread.  A fixed buffer: reporting an
+// error allocates nothing.
+thread_local char g_last_error[512] = "";
 
-int fail(int code, const std::string& msg) {
-    g_last_error = msg;
+int fail(int code, const char* msg) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
     return code;
 }
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(MHDPIC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+int fail_hip(const char* what, hipError_t e) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return MHDPIC_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return fail_hip(#expr, e_); \
     } while (0)
 
 constexpr size_t kAlign = 256;
@@ -60,7 +65,7 @@ size_t push_lds_bytes(int ndim, int prec, const TileShape& t) {
     size_t FOFF = ndim == 3 ? PX * PY : PX;
     size_t NFF = NP - 2 * FOFF;
     size_t fsz = prec == MHDPIC_FP64 ? 8 : 4;
-    return NFF * 4 * 8 + NP * 4 * 8 + NFF * 6 * fsz;
+    return NFF * 4 * 8 + NP * 4 * 8 + NFF * 6 * fsz + NP * 4;
 }
 
 bool tile_compiled(int ndim, const TileShape& t) {
@@ -84,9 +89,10 @@ TileShape default_tile(int ndim, int prec) {
 }
 
 struct Layout {
-    // sizes
-    int64_t N = 0, NC = 0;
+    // sizes: N particle slots (the capacity), N0 particles at initialisation
+    int64_t N = 0, N0 = 0, NC = 0;
     int32_t NT = 0, NW = 0;
+    bool tagged = false;  // particles carry tags (the context has a capacity for additions)
     // offsets into the workspace
     size_t partA = 0, partB = 0, part_bytes = 0;
     size_t key = 0, code = 0, EB = 0, Dcorr = 0, nJ0 = 0, nJ1 = 0;
@@ -94,7 +100,7 @@ struct Layout {
     size_t items[2] = {0, 0}, n_items[2] = {0, 0}, item_first[2] = {0, 0};
     size_t cnt = 0, off = 0;
     int K = 27;
-    size_t boxes = 0, part_off = 0, cell_off = 0;
+    size_t boxes = 0, part_off = 0, cell_off = 0, box_count = 0, n_out = 0;
     size_t total = 0;
 };
 
@@ -120,7 +126,6 @@ struct mhdpic_ctx {
     TileShape tile{};
     std::vector<mhdpic_box> boxes;
     std::vector<BoxDev> bdev;
-    std::vector<int64_t> part_off, cell_off;
     Layout L;
     unsigned char* ws = nullptr;
     int cur = 0;   // which particle buffer (0 = A, 1 = B) holds the state
@@ -139,6 +144,8 @@ struct mhdpic_ctx {
     std::vector<Mark> marks;
     std::vector<hipEvent_t> pool;
     bool dt_uploaded = false;
+    int64_t n_init = 0;   // particles given at initialisation (ids 0 .. n_init-1)
+    int32_t next_id = 0;  // id of the next added particle
     // cached graph of mhdpic_step_graph
     hipGraphExec_t graph_exec = nullptr;
     GraphKey graph_key;
@@ -182,10 +189,20 @@ int validate_boxes(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
         if (B.hall && !(B.qomc_gas != 0.0 && std::isfinite(B.qomc_gas)))
             return fail(MHDPIC_EINVAL, "qomc_gas must be finite and nonzero with hall = 1");
         if (np[b] < 0) return fail(MHDPIC_EINVAL, "negative particle count");
-        N += np[b];
+        if (B.capacity < 0) return fail(MHDPIC_EINVAL, "negative capacity");
+        for (int d = 0; d < 3; ++d) {
+            const int32_t lo = B.boundary[d][0], hi = B.boundary[d][1];
+            if (lo < MHDPIC_PERIODIC || lo > MHDPIC_ABSORB || hi < MHDPIC_PERIODIC || hi > MHDPIC_ABSORB)
+                return fail(MHDPIC_EINVAL, "boundary must be MHDPIC_PERIODIC, MHDPIC_REFLECT or MHDPIC_ABSORB");
+            if ((lo == MHDPIC_PERIODIC) != (hi == MHDPIC_PERIODIC))
+                return fail(MHDPIC_EINVAL, "an axis is periodic on both faces or on neither");
+            if (lo != MHDPIC_PERIODIC && (d >= ndim || B.n[d] < 2))
+                return fail(MHDPIC_EINVAL, "a non-periodic axis needs at least 2 cells (and z only in 3D)");
+        }
+        N += std::max<int64_t>(np[b], B.capacity);
         NC += (int64_t)B.n[0] * B.n[1] * (ndim == 3 ? B.n[2] : 1);
     }
-    if (N >= (int64_t)1 << 31) return fail(MHDPIC_ERANGE, "at most 2^31-1 particles");
+    if (N >= (int64_t)1 << 31) return fail(MHDPIC_ERANGE, "at most 2^31-1 particle slots");
     if (NC >= (int64_t)1 << 31) return fail(MHDPIC_ERANGE, "at most 2^31-1 cells");
     return MHDPIC_OK;
 }
@@ -195,7 +212,9 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     Layout L;
     for (int b = 0; b < nb; ++b) {
         const mhdpic_box& B = boxes[b];
-        L.N += np[b];
+        L.N += std::max<int64_t>(np[b], B.capacity);
+        L.N0 += np[b];
+        L.tagged = L.tagged || B.capacity > 0;
         L.NC += (int64_t)B.n[0] * B.n[1] * (ndim == 3 ? B.n[2] : 1);
         int ntx = (B.n[0] + tile.x - 1) / tile.x, nty = (B.n[1] + tile.y - 1) / tile.y;
         int ntz = ndim == 3 ? (B.n[2] + tile.z - 1) / tile.z : 1;
@@ -204,9 +223,9 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     L.NW = L.NT + (int32_t)(L.N / kItemParticles) + 1;
     const size_t N = (size_t)L.N, NC = (size_t)L.NC;
     const size_t fsz = precision == MHDPIC_FP64 ? 8 : 4;
-    // cell, d[ndim], v[3], m, qm (fsz each), pid
+    // cell, d[ndim], v[3], m, qm (fsz each), pid, tags (binary64, if any)
     L.part_bytes = align_up(N * 4) + (size_t)ndim * align_up(N * fsz) + 3 * align_up(N * fsz) +
-                   2 * align_up(N * fsz) + align_up(N * 4);
+                   2 * align_up(N * fsz) + align_up(N * 4) + (L.tagged ? align_up(N * 8) : 0);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
@@ -237,12 +256,14 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     L.boxes = take((size_t)nb * sizeof(BoxDev));
     L.part_off = take((size_t)(nb + 1) * 8);
     L.cell_off = take((size_t)(nb + 1) * 8);
+    L.box_count = take((size_t)nb * 8);
+    L.n_out = take(4);
     L.total = o;
     return L;
 }
 
 template <typename PS, typename T>
-PS carve_particles(unsigned char* base, size_t N, int ndim) {
+PS carve_particles(unsigned char* base, size_t N, int ndim, bool tagged) {
     PS P{};
     size_t o = 0;
     P.cell = reinterpret_cast<uint32_t*>(base + o);
@@ -264,13 +285,15 @@ PS carve_particles(unsigned char* base, size_t N, int ndim) {
     P.qm = reinterpret_cast<T*>(base + o);
     o += align_up(N * sizeof(T));
     P.pid = reinterpret_cast<int32_t*>(base + o);
+    o += align_up(N * 4);
+    P.tag = tagged ? reinterpret_cast<double*>(base + o) : nullptr;
     return P;
 }
 
 template <typename PS, typename T>
 PS part(mhdpic_ctx* c, int which) {
     size_t off = which == 0 ? c->L.partA : c->L.partB;
-    return carve_particles<PS, T>(c->ws + off, (size_t)c->L.N, c->ndim);
+    return carve_particles<PS, T>(c->ws + off, (size_t)c->L.N, c->ndim, c->L.tagged);
 }
 
 template <typename T>
@@ -347,27 +370,44 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
                        at<int32_t>(c, L.tile_box), bd, at<uint32_t>(c, L.start),
                        at<uint32_t>(c, L.item_first[1 - it]), at<WorkItem>(c, L.items[1 - it]),
                        L.NT, kItemParticles);
-    hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256>), dim3(item_grid(L)), dim3(256), 0, s, A, Bo,
-                       at<uint16_t>(c, L.code), at<uint32_t>(c, L.off), at<WorkItem>(c, L.items[it]),
-                       at<uint32_t>(c, L.n_items[it]));
+    if (L.tagged)
+        hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256, true>), dim3(item_grid(L)), dim3(256), 0, s,
+                           A, Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
+                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
+    else
+        hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256, false>), dim3(item_grid(L)), dim3(256), 0, s,
+                           A, Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
+                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
     c->cur = 1 - c->cur;
     c->it = 1 - it;
     return MHDPIC_OK;
 }
 
-// First binning of a new context: any tile, by the particles' current cells,
-// from buffer 0 into buffer 1.
+// Box lookup of the slots of the current buffer: its first n_old slots are
+// grouped by tile (the last sort or binning wrote start[]), new particles
+// follow box by box as the part_off table says.
+SlotBoxes slot_boxes(mhdpic_ctx* c, int64_t n_old) {
+    const Layout& L = c->L;
+    return SlotBoxes{at<uint32_t>(c, L.start), at<int32_t>(c, L.tile_box), L.NT, n_old,
+                     at<int64_t>(c, L.part_off), c->nb};
+}
+
+// Sorts the n_src particles of the current buffer by the tile of their cell
+// into the other buffer, dropping those that have left their box, and
+// rebuilds the work list: the first sort of a context (n_old = 0) and the
+// re-sorts after particles are added or removed.
 template <int NDIM, typename PS, typename T>
-int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
+int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n_src, int64_t n_old) {
     const Layout& L = c->L;
     const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
-    PS A = part<PS, T>(c, 0);
-    PS Bo = part<PS, T>(c, 1);
+    PS A = part<PS, T>(c, c->cur);
+    PS Bo = part<PS, T>(c, 1 - c->cur);
+    const SlotBoxes sb = slot_boxes(c, n_old);
     fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
     // per-block LDS histograms when the tiles fit (up to 128 KB of LDS), else
     // one atomic per distinct tile in each wave
     const bool lds = L.NT <= kSortLdsTiles;
-    const unsigned gC = (unsigned)((L.N + kSortChunk - 1) / kSortChunk);
+    const unsigned gC = (unsigned)((n_src + kSortChunk - 1) / kSortChunk);
     const size_t hbytes = (size_t)L.NT * sizeof(uint32_t);
     if (lds && hbytes > 65536) {
         HIP_TRY(hipFuncSetAttribute((const void*)k_key_count_lds<NDIM, PS>,
@@ -375,44 +415,43 @@ int launch_initial_sort(mhdpic_ctx* c, hipStream_t s) {
         HIP_TRY(hipFuncSetAttribute((const void*)k_scatter_lds<NDIM, PS>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)hbytes));
     }
-    if (L.N > 0 && lds)
+    if (n_src > 0 && lds)
         hipLaunchKernelGGL((k_key_count_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           at<int64_t>(c, L.part_off), c->nb, L.N, T3, L.NT);
-    else if (L.N > 0)
-        hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A,
+                           sb, n_src, T3, L.NT);
+    else if (n_src > 0)
+        hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(n_src, 256)), dim3(256), 0, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           at<int64_t>(c, L.part_off), c->nb, L.N, T3);
+                           sb, n_src, T3);
+    // the scan rewrites start[]: the box lookup above must have finished
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
                        at<uint32_t>(c, L.start), at<uint32_t>(c, L.cursor), at<int32_t>(c, L.tile_box),
                        at<WorkItem>(c, L.items[0]), at<uint32_t>(c, L.item_first[0]),
                        at<uint32_t>(c, L.n_items[0]), L.NT, kItemParticles);
-    if (L.N > 0 && lds)
+    if (n_src > 0 && lds)
         hipLaunchKernelGGL((k_scatter_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A, Bo,
-                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N, L.NT);
-    else if (L.N > 0)
-        hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, A, Bo,
-                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), L.N);
-    c->cur = 1;
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n_src, L.NT);
+    else if (n_src > 0)
+        hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(n_src, 256)), dim3(256), 0, s, A, Bo,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n_src);
+    c->cur = 1 - c->cur;
     c->it = 0;
     return MHDPIC_OK;
 }
 
-int launch_initial_sort_any(mhdpic_ctx* c, hipStream_t s) {
+int launch_sort_any(mhdpic_ctx* c, hipStream_t s, int64_t n_src, int64_t n_old) {
     if (c->precision == MHDPIC_FP64) {
-        if (c->ndim == 2) return launch_initial_sort<2, PartF64, double>(c, s);
-        return launch_initial_sort<3, PartF64, double>(c, s);
+        if (c->ndim == 2) return launch_sort<2, PartF64, double>(c, s, n_src, n_old);
+        return launch_sort<3, PartF64, double>(c, s, n_src, n_old);
     }
-    if (c->ndim == 2) return launch_initial_sort<2, PartF32, float>(c, s);
-    return launch_initial_sort<3, PartF32, float>(c, s);
+    if (c->ndim == 2) return launch_sort<2, PartF32, float>(c, s, n_src, n_old);
+    return launch_sort<3, PartF32, float>(c, s, n_src, n_old);
 }
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
 int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
-    // Two blocks of eight waves (four per SIMD) where the kernel fits in 128
-    // VGPRs: 2D, and 3D in binary32.  The binary64 3D kernel needs more
-    // registers, and its 70 KB of LDS allow two blocks of four waves.
-    constexpr int BLOCK = (NDIM == 2 || std::is_same<typename Pol::R, float>::value) ? 512 : 256;
+    // two blocks of eight waves per CU (four per SIMD)
+    constexpr int BLOCK = PushShape<Pol, NDIM>::BLOCK;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     const Layout& L = c->L;
@@ -448,11 +487,12 @@ int launch_init_deposit_pol(mhdpic_ctx* c, hipStream_t s) {
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     const Layout& L = c->L;
-    const size_t lds = (size_t)G::NP * 4 * 8;
+    const size_t lds = (size_t)G::NP * 4 * 8 + (size_t)G::NP * 4;
     auto kern = k_deposit_nJ_tiled<Pol, NDIM, TX, TY, TZ, BLOCK>;
     if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s,
-                       part<typename Pol::Part, R>(c, c->cur), at<int64_t>(c, L.nJ0), L.NC,
+                       part<typename Pol::Part, R>(c, c->cur),
+                       at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1), L.NC,
                        at<BoxDev>(c, L.boxes), at<WorkItem>(c, L.items[c->it]),
                        at<uint32_t>(c, L.n_items[c->it]), at<uint32_t>(c, L.err));
     return MHDPIC_OK;
@@ -565,25 +605,41 @@ int post_error_copy(mhdpic_ctx* c, hipStream_t s) {
     return MHDPIC_OK;
 }
 
-int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
-                    const double* dt, int32_t n_steps, int32_t n_sub) {
-    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+// Checks the arguments of a step call against the boxes (move limit per box).
+int check_step_boxes(const mhdpic_box* boxes, int32_t nb, int ndim, int64_t NC, const double* B,
+                     const double* vg, const double* rho, const double* dt, int32_t n_steps,
+                     int32_t n_sub) {
     if (!dt || n_steps < 0) return fail(MHDPIC_EINVAL, "dt is NULL or n_steps < 0");
     if (n_sub < 1 || n_sub > kMaxSubsteps) return fail(MHDPIC_EINVAL, "n_sub out of range");
-    if (c->L.NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
+    if (NC > 0 && (!B || !vg)) return fail(MHDPIC_EINVAL, "B or vg is NULL");
     bool any_hall = false;
-    for (auto& b : c->boxes) any_hall |= b.hall != 0;
+    for (int b = 0; b < nb; ++b) any_hall |= boxes[b].hall != 0;
     if (any_hall && !rho) return fail(MHDPIC_EINVAL, "rho is NULL with hall = 1");
-    for (int b = 0; b < c->nb; ++b) {
-        const mhdpic_box& bx = c->boxes[b];
+    for (int b = 0; b < nb; ++b) {
+        const mhdpic_box& bx = boxes[b];
         if (!std::isfinite(dt[b])) return fail(MHDPIC_EINVAL, "dt must be finite");
-        for (int d = 0; d < c->ndim; ++d) {
+        for (int d = 0; d < ndim; ++d) {
             double cells = bx.C * std::fabs(dt[b] / (double)n_sub) / bx.dx[d];
             if (!(cells <= bx.max_move_cells * (1.0 - 1e-12)))
                 return fail(MHDPIC_ERANGE, "C*|dt|/dx exceeds max_move_cells");
         }
     }
     return MHDPIC_OK;
+}
+
+int check_step_args(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
+                    const double* dt, int32_t n_steps, int32_t n_sub) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    return check_step_boxes(c->boxes.data(), c->nb, c->ndim, c->L.NC, B, vg, rho, dt, n_steps, n_sub);
+}
+
+// The per-call step constants of one box: the particle step dt/n_sub, its
+// half, and the half step in cells per unit velocity along each axis.
+void set_step(BoxDev& d, const mhdpic_box& B, int ndim, double dt, int32_t n_sub) {
+    const double dts = dt / (double)n_sub;
+    d.dt = dts;
+    d.hdt = 0.5 * dts;
+    for (int k = 0; k < 3; ++k) d.hdx[k] = k < ndim ? d.hdt / B.dx[k] : 0.0;
 }
 
 // Refreshes the per-call step constants on the device when dt changed.  A
@@ -595,13 +651,7 @@ int set_dt(mhdpic_ctx* c, const double* dt, int32_t n_sub, hipStream_t s, bool c
     if (!changed) return MHDPIC_OK;
     if (capturing)
         return fail(MHDPIC_EINVAL, "dt differs from the last call: step once before capturing");
-    for (int b = 0; b < c->nb; ++b) {
-        BoxDev& d = c->bdev[b];
-        const double dts = dt[b] / (double)n_sub;  // the particle step
-        d.dt = dts;
-        d.hdt = 0.5 * dts;
-        for (int k = 0; k < 3; ++k) d.hdx[k] = k < c->ndim ? d.hdt / c->boxes[b].dx[k] : 0.0;
-    }
+    for (int b = 0; b < c->nb; ++b) set_step(c->bdev[b], c->boxes[b], c->ndim, dt[b], n_sub);
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.boxes, c->bdev.data(), sizeof(BoxDev) * c->nb,
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // the host copy may change after return
@@ -652,13 +702,283 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
 
 }  // namespace
 
+namespace {
+
+std::vector<TileShape> tile_candidates(int ndim, int prec) {
+    std::vector<TileShape> all = ndim == 2
+        ? std::vector<TileShape>{{16, 16, 1}, {32, 16, 1}, {8, 8, 1}, {32, 32, 1}, {64, 16, 1}}
+        : std::vector<TileShape>{{8, 4, 4}, {8, 8, 4}, {4, 4, 4}, {8, 8, 8}, {16, 4, 4}};
+    std::vector<TileShape> ok;
+    for (const TileShape& t : all)
+        if (tile_supported(ndim, prec, t)) ok.push_back(t);
+    return ok;
+}
+
+std::vector<mhdpic_box> with_tile(const mhdpic_box* boxes, int32_t nb, const TileShape& t) {
+    std::vector<mhdpic_box> v(boxes, boxes + nb);
+    for (auto& b : v) {
+        b.tile[0] = t.x;
+        b.tile[1] = t.y;
+        b.tile[2] = b.ndim == 3 ? t.z : 1;
+    }
+    return v;
+}
+
+}  // namespace
+
+namespace {
+
+// The device record of box B.  cell_off, part_off and tile_off are the cells,
+// particles and tiles of the boxes before it; the step constants stay zero
+// until a step sets them.
+BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int64_t cell_off,
+                   int64_t part_off, int64_t np, int32_t tile_off) {
+    BoxDev d{};
+    for (int k = 0; k < 3; ++k) {
+        d.n[k] = (k < ndim) ? B.n[k] : 1;
+        d.dx[k] = (k < ndim) ? B.dx[k] : 1.0;
+        d.x0[k] = (k < ndim) ? B.x0[k] : 0.0;
+    }
+    const int T[3] = {tile.x, tile.y, ndim == 3 ? tile.z : 1};
+    for (int k = 0; k < 3; ++k) {
+        d.nt[k] = (d.n[k] + T[k] - 1) / T[k];
+        d.small_last[k] = (d.nt[k] >= 2 && d.n[k] % T[k] == 1) ? 1 : 0;
+    }
+    d.tile_off = tile_off;
+    for (int k = 0; k < 3; ++k) {
+        d.face[k][0] = B.boundary[k][0];
+        d.face[k][1] = B.boundary[k][1];
+    }
+    d.hall = B.hall;
+    d.cell_off = cell_off;
+    d.part_off = part_off;
+    d.part_n = np;
+    d.C = B.C;
+    d.C2 = B.C * B.C;
+    d.iC = 1.0 / B.C;
+    d.qg = B.qomc_gas;
+    d.S = std::ldexp(1.0, B.frac_bits);
+    d.iS = std::ldexp(1.0, -B.frac_bits);
+    d.dV = B.dx[0] * B.dx[1];
+    if (ndim == 3) d.dV = d.dV * B.dx[2];
+    return d;
+}
+
+// Host fields of a context over the caller's workspace; nothing is enqueued.
+int open_context(mhdpic_ctx* c, const mhdpic_box* boxes, int32_t n_boxes, const int64_t* np,
+                 int32_t precision, void* workspace, size_t ws_bytes, const double* x,
+                 const double* v, const double* m, const double* qm) {
+    int ndim;
+    TileShape tile;
+    int rc = validate_boxes(boxes, n_boxes, np, precision, ndim, tile);
+    if (rc) return rc;
+    Layout L = make_layout(boxes, n_boxes, np, precision, ndim, tile);
+    if (!workspace) return fail(MHDPIC_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace) % kAlign) return fail(MHDPIC_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(MHDPIC_ENOMEM, "workspace too small");
+    if (L.N0 > 0 && (!x || !v || !m || !qm)) return fail(MHDPIC_EINVAL, "particle arrays are NULL");
+    c->ndim = ndim;
+    c->precision = precision;
+    c->nb = n_boxes;
+    c->tile = tile;
+    c->L = L;
+    c->ws = static_cast<unsigned char*>(workspace);
+    return MHDPIC_OK;
+}
+
+// Waits for the stream and returns the latched device error (then clears it).
+// The word is read into host memory of the caller's stack.
+int read_error_now(mhdpic_ctx* c, hipStream_t s) {
+    uint32_t bits = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, c->ws + c->L.err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bits) {
+        fill_u32(at<uint32_t>(c, c->L.err), 1, 0u, s);
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(code_of(bits), msg_of(bits));
+    }
+    return MHDPIC_OK;
+}
+
+// Converts n new particles (global positions, [3][n] arrays) of the boxes the
+// part_off table describes into slots slot0.. of the current buffer, with ids
+// pid0 + j.
+void launch_convert(mhdpic_ctx* c, hipStream_t s, const double* x, const double* v,
+                    const double* m, const double* qm, const double* tag, int64_t n, int64_t slot0,
+                    int32_t pid0) {
+    if (n <= 0) return;
+    const Layout& L = c->L;
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const int64_t* po = at<int64_t>(c, L.part_off);
+    uint32_t* err = at<uint32_t>(c, L.err);
+    const unsigned g = grid_for(n, 256);
+    if (c->precision == MHDPIC_FP64) {
+        PartF64 P = part<PartF64, double>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(g), dim3(256), 0, s, P, x, v, m,
+                               qm, tag, bd, po, c->nb, n, slot0, pid0, err);
+        else
+            hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(g), dim3(256), 0, s, P, x, v, m,
+                               qm, tag, bd, po, c->nb, n, slot0, pid0, err);
+    } else {
+        PartF32 P = part<PartF32, float>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(g), dim3(256), 0, s, P, x, v, m,
+                               qm, tag, bd, po, c->nb, n, slot0, pid0, err);
+        else
+            hipLaunchKernelGGL((k_init_convert<3, PartF32, float>), dim3(g), dim3(256), 0, s, P, x, v, m,
+                               qm, tag, bd, po, c->nb, n, slot0, pid0, err);
+    }
+}
+
+// Enqueues the set-up of a context opened by open_context and waits for it:
+// box records (with the step constants of dt/n_sub when dt is given), the
+// per-box and per-tile tables, conversion of the global positions to (cell,
+// offset) form, the first sort and the n_CR, J_CR deposit at the initial
+// positions (App. A.3 predictor).  The box records pass through a small host
+// buffer in chunks; keep, if given, receives all of them.  Returns the error
+// latched by the kernels.
+int init_device(mhdpic_ctx* c, const mhdpic_box* boxes, const int64_t* np, const double* dt,
+                int32_t n_sub, const double* x, const double* v, const double* m,
+                const double* qm, const double* tag, hipStream_t s, BoxDev* keep) {
+    const Layout& L = c->L;
+    const int nb = c->nb;
+    constexpr int kChunk = 16;
+    BoxDev chunk[kChunk];
+    int64_t cell_off = 0, part_off = 0;
+    int32_t tile_off = 0;
+    for (int b0 = 0; b0 < nb; b0 += kChunk) {
+        const int nc = std::min(kChunk, nb - b0);
+        for (int k = 0; k < nc; ++k) {
+            const mhdpic_box& B = boxes[b0 + k];
+            BoxDev d = make_boxdev(B, c->ndim, c->tile, cell_off, part_off, np[b0 + k], tile_off);
+            if (dt) set_step(d, B, c->ndim, dt[b0 + k], n_sub);
+            cell_off += (int64_t)d.n[0] * d.n[1] * d.n[2];
+            part_off += np[b0 + k];
+            tile_off += d.nt[0] * d.nt[1] * d.nt[2];
+            chunk[k] = d;
+            if (keep) keep[b0 + k] = d;
+        }
+        HIP_TRY(hipMemcpyAsync(c->ws + L.boxes + sizeof(BoxDev) * b0, chunk, sizeof(BoxDev) * nc,
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // the chunk buffer is reused
+    }
+    c->dt_uploaded = dt != nullptr;
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const int64_t nt = std::max<int64_t>(L.NT, nb + 1);
+    hipLaunchKernelGGL(k_box_tables, dim3(grid_for(nt, 256)), dim3(256), 0, s, bd, nb,
+                       at<int64_t>(c, L.part_off), at<int64_t>(c, L.cell_off),
+                       at<int32_t>(c, L.tile_box), L.NT);
+    fill_u32(at<uint32_t>(c, L.err), 1, 0u, s);
+    fill_i64(at<int64_t>(c, L.Dcorr), 4 * L.NC, s);
+    fill_i64(at<int64_t>(c, L.nJ0), 4 * L.NC, s);
+    c->cur = 0;
+    c->nj = 0;
+    launch_convert(c, s, x, v, m, qm, tag, L.N0, 0, 0);
+    c->n_init = L.N0;
+    c->next_id = (int32_t)L.N0;
+    int rc = launch_sort_any(c, s, L.N0, 0);
+    if (rc) return rc;
+    if (L.N0 > 0) {
+        rc = launch_init_deposit(c, s);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGetLastError());
+    return read_error_now(c, s);
+}
+
+// Particles in the order of their initial ids into [3][N0] arrays; columns
+// of particles that have left their box read NaN.  Not defined once particles
+// were added (their ids lie beyond N0).
+int read_particles(mhdpic_ctx* c, double* x, double* v, hipStream_t s) {
+    const Layout& L = c->L;
+    if (c->next_id != c->n_init)
+        return fail(MHDPIC_ESTATE, "particles were added: read them with mhdpic_particles_read_ids");
+    if (c->n_init == 0) return MHDPIC_OK;
+    const BoxDev* bd = at<BoxDev>(c, L.boxes);
+    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
+    const unsigned g = grid_for(L.N, 256);
+    const double nan = std::nan("");
+    const unsigned gf = (unsigned)std::min<int64_t>(grid_for(3 * c->n_init, 256), 8192);
+    hipLaunchKernelGGL(k_fill_f64, dim3(gf), dim3(256), 0, s, x, 3 * c->n_init, nan);
+    hipLaunchKernelGGL(k_fill_f64, dim3(gf), dim3(256), 0, s, v, 3 * c->n_init, nan);
+    const int64_t N = c->n_init, cap = L.N;
+    if (c->precision == MHDPIC_FP64) {
+        PartF64 P = part<PartF64, double>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_read_particles<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+        else
+            hipLaunchKernelGGL((k_read_particles<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+    } else {
+        PartF32 P = part<PartF32, float>(c, c->cur);
+        if (c->ndim == 2)
+            hipLaunchKernelGGL((k_read_particles<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+        else
+            hipLaunchKernelGGL((k_read_particles<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+    }
+    HIP_TRY(hipGetLastError());
+    return MHDPIC_OK;
+}
+
+int read_deposits(mhdpic_ctx* c, int64_t* out, hipStream_t s) {
+    const int64_t NC = c->L.NC;
+    if (NC == 0) return MHDPIC_OK;
+    const int64_t* nJ = at<int64_t>(c, c->nj == 0 ? c->L.nJ0 : c->L.nJ1);
+    HIP_TRY(hipMemcpyAsync(out, nJ, 4 * NC * 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(out + 4 * NC, at<int64_t>(c, c->L.Dcorr), 4 * NC * 8,
+                           hipMemcpyDeviceToDevice, s));
+    return MHDPIC_OK;
+}
+
+// One call from global particles to stepped particles and deposits, through
+// a context that lives on this function's stack and in `ws` (nothing of it is
+// kept): open, set up with the step constants, n_steps steps, read back.
+// Waits for the stream.  Host memory: the context's fixed fields and a
+// 16-record staging buffer, both on the stack.
+int advance_impl(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* np, int32_t precision,
+                 const double* x, const double* v, const double* m, const double* qm,
+                 const double* B, const double* vg, const double* rho, const double* dt,
+                 int32_t n_steps, int32_t n_sub, double* x_out, double* v_out, int64_t* dep_out,
+                 void* ws, size_t ws_bytes, hipStream_t s) {
+    mhdpic_ctx c;
+    int rc = open_context(&c, boxes, n_boxes, np, precision, ws, ws_bytes, x, v, m, qm);
+    if (rc) return rc;
+    rc = check_step_boxes(boxes, n_boxes, c.ndim, c.L.NC, B, vg, rho, dt, n_steps, n_sub);
+    if (rc) return rc;
+    if ((c.L.N0 > 0 && (!x_out || !v_out)) || (c.L.NC > 0 && !dep_out))
+        return fail(MHDPIC_EINVAL, "x_out, v_out or deposits_out is NULL");
+    c.last_stream = s;
+    rc = init_device(&c, boxes, np, dt, n_sub, x, v, m, qm, nullptr, s, nullptr);
+    if (rc) return rc;
+    if (n_steps > 0) rc = enqueue_steps(&c, B, vg, rho, n_steps, n_sub, s, false);
+    if (!rc) rc = read_particles(&c, x_out, v_out, s);
+    if (!rc) rc = read_deposits(&c, dep_out, s);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return read_error_now(&c, s);
+}
+
+}  // namespace
+
+namespace {
+
+// n_CR, J_CR of the current particles at their positions, from scratch (after
+// particles were added or removed: the same integers as adding or taking
+// back each particle's own).
+int relaunch_nJ(mhdpic_ctx* c, hipStream_t s) {
+    fill_i64(at<int64_t>(c, c->nj == 0 ? c->L.nJ0 : c->L.nJ1), 4 * c->L.NC, s);
+    return launch_init_deposit(c, s);
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
 
 extern "C" {
 
-const char* mhdpic_last_error(void) { return g_last_error.c_str(); }
+const char* mhdpic_last_error(void) { return g_last_error; }
 
 int mhdpic_workspace_size(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
                           int32_t precision, size_t* bytes) {
@@ -677,140 +997,40 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
                 mhdpic_ctx** out) {
     if (!out) return fail(MHDPIC_EINVAL, "out is NULL");
     *out = nullptr;
-    int ndim;
-    TileShape tile;
-    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
-    if (rc) return rc;
-    Layout L = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile);
-    if (!workspace) return fail(MHDPIC_EINVAL, "workspace is NULL");
-    if (((uintptr_t)workspace) % kAlign) return fail(MHDPIC_EINVAL, "workspace must be 256-byte aligned");
-    if (ws_bytes < L.total) return fail(MHDPIC_ENOMEM, "workspace too small");
-    if (L.N > 0 && (!x || !v || !m || !qm)) return fail(MHDPIC_EINVAL, "particle arrays are NULL");
-
     mhdpic_ctx* c = new mhdpic_ctx();
-    c->ndim = ndim;
-    c->precision = precision;
-    c->nb = n_boxes;
-    c->tile = tile;
-    c->L = L;
-    c->ws = static_cast<unsigned char*>(workspace);
-    c->boxes.assign(boxes, boxes + n_boxes);
-    c->part_off.assign(n_boxes + 1, 0);
-    c->cell_off.assign(n_boxes + 1, 0);
-    std::vector<int32_t> tile_box;
-    int32_t toff = 0;
-    for (int b = 0; b < n_boxes; ++b) {
-        const mhdpic_box& B = boxes[b];
-        BoxDev d{};
-        for (int k = 0; k < 3; ++k) {
-            d.n[k] = (k < ndim) ? B.n[k] : 1;
-            d.dx[k] = (k < ndim) ? B.dx[k] : 1.0;
-            d.x0[k] = (k < ndim) ? B.x0[k] : 0.0;
-        }
-        int T[3] = {tile.x, tile.y, ndim == 3 ? tile.z : 1};
-        for (int k = 0; k < 3; ++k) {
-            d.nt[k] = (d.n[k] + T[k] - 1) / T[k];
-            d.small_last[k] = (d.nt[k] >= 2 && d.n[k] % T[k] == 1) ? 1 : 0;
-        }
-        d.tile_off = toff;
-        int ntiles = d.nt[0] * d.nt[1] * d.nt[2];
-        for (int t = 0; t < ntiles; ++t) tile_box.push_back(b);
-        toff += ntiles;
-        d.hall = B.hall;
-        d.cell_off = c->cell_off[b];
-        d.part_off = c->part_off[b];
-        d.part_n = n_particles[b];
-        c->part_off[b + 1] = c->part_off[b] + n_particles[b];
-        c->cell_off[b + 1] = c->cell_off[b] + (int64_t)d.n[0] * d.n[1] * d.n[2];
-        d.C = B.C;
-        d.C2 = B.C * B.C;
-        d.iC = 1.0 / B.C;
-        d.qg = B.qomc_gas;
-        d.S = std::ldexp(1.0, B.frac_bits);
-        d.iS = std::ldexp(1.0, -B.frac_bits);
-        d.dV = B.dx[0] * B.dx[1];
-        if (ndim == 3) d.dV = d.dV * B.dx[2];
-        d.dt = d.hdt = 0.0;
-        d.hdx[0] = d.hdx[1] = d.hdx[2] = 0.0;
-        c->bdev.push_back(d);
-    }
+    int rc = open_context(c, boxes, n_boxes, n_particles, precision, workspace, ws_bytes, x, v, m, qm);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     c->last_stream = s;
-    auto cleanup = [&](int code) {
+    if (!rc && hipHostMalloc((void**)&c->err_host, 4, hipHostMallocDefault) != hipSuccess)
+        rc = fail(MHDPIC_EDEVICE, "hipHostMalloc failed");
+    if (!rc) {
+        *c->err_host = 0;
+        if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess)
+            rc = fail(MHDPIC_EDEVICE, "hipEventCreate failed");
+    }
+    if (!rc) {
+        c->boxes.assign(boxes, boxes + n_boxes);
+        c->bdev.resize(n_boxes);
+        rc = init_device(c, boxes, n_particles, nullptr, 1, x, v, m, qm, nullptr, s, c->bdev.data());
+    }
+    if (rc) {
         if (c->err_host) (void)hipHostFree(c->err_host);
         if (c->err_event) (void)hipEventDestroy(c->err_event);
         delete c;
-        return code;
-    };
-    if (hipHostMalloc((void**)&c->err_host, 4, hipHostMallocDefault) != hipSuccess)
-        return cleanup(fail(MHDPIC_EDEVICE, "hipHostMalloc failed"));
-    *c->err_host = 0;
-    if (hipEventCreateWithFlags(&c->err_event, hipEventDisableTiming) != hipSuccess)
-        return cleanup(fail(MHDPIC_EDEVICE, "hipEventCreate failed"));
-
-#define INIT_TRY(expr)                                                                        \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return cleanup(fail(MHDPIC_EDEVICE, std::string(#expr) + ": " + \
-                                                                      hipGetErrorString(e_))); \
-    } while (0)
-
-    INIT_TRY(hipMemcpyAsync(c->ws + L.boxes, c->bdev.data(), sizeof(BoxDev) * n_boxes,
-                            hipMemcpyHostToDevice, s));
-    INIT_TRY(hipMemcpyAsync(c->ws + L.part_off, c->part_off.data(), 8 * (n_boxes + 1),
-                            hipMemcpyHostToDevice, s));
-    INIT_TRY(hipMemcpyAsync(c->ws + L.cell_off, c->cell_off.data(), 8 * (n_boxes + 1),
-                            hipMemcpyHostToDevice, s));
-    INIT_TRY(hipMemcpyAsync(c->ws + L.tile_box, tile_box.data(), 4 * tile_box.size(),
-                            hipMemcpyHostToDevice, s));
-    INIT_TRY(hipStreamSynchronize(s));
-    fill_u32(at<uint32_t>(c, L.err), 1, 0u, s);
-    fill_i64(at<int64_t>(c, L.Dcorr), 4 * L.NC, s);
-    fill_i64(at<int64_t>(c, L.nJ0), 4 * L.NC, s);
-    c->cur = 0;
-    c->nj = 0;
-    const BoxDev* bd = at<BoxDev>(c, L.boxes);
-    const int64_t* po = at<int64_t>(c, L.part_off);
-    const unsigned gN = grid_for(L.N, 256);
-    if (L.N > 0) {
-        if (precision == MHDPIC_FP64) {
-            PartF64 P = part<PartF64, double>(c, 0);
-            if (ndim == 2)
-                hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(gN), dim3(256), 0, s,
-                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            else
-                hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(gN), dim3(256), 0, s,
-                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-        } else {
-            PartF32 P = part<PartF32, float>(c, 0);
-            if (ndim == 2)
-                hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(gN), dim3(256), 0, s,
-                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-            else
-                hipLaunchKernelGGL((k_init_convert<3, PartF32, float>), dim3(gN), dim3(256), 0, s,
-                                   P, x, v, m, qm, bd, po, n_boxes, L.N, at<uint32_t>(c, L.err));
-        }
+        return rc;
     }
-    {
-        int rc0 = launch_initial_sort_any(c, s);
-        if (rc0) return cleanup(rc0);
-    }
-    if (L.N > 0) {
-        int rc0 = launch_init_deposit(c, s);
-        if (rc0) return cleanup(rc0);
-    }
-    INIT_TRY(hipGetLastError());
-    uint32_t bits = 0;
-    INIT_TRY(hipMemcpyAsync(&bits, c->ws + L.err, 4, hipMemcpyDeviceToHost, s));
-    INIT_TRY(hipStreamSynchronize(s));
-    if (bits) {
-        int code = code_of(bits);
-        std::string msg = msg_of(bits);
-        return cleanup(fail(code, msg));
-    }
-#undef INIT_TRY
     *out = c;
     return MHDPIC_OK;
+}
+
+int mhdpic_advance(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                   int32_t precision, const double* x, const double* v, const double* m,
+                   const double* qm, const double* B, const double* vg, const double* rho,
+                   const double* dt, int32_t n_steps, int32_t n_sub, double* x_out, double* v_out,
+                   int64_t* deposits_out, void* workspace, size_t ws_bytes, void* hip_stream) {
+    return advance_impl(boxes, n_boxes, n_particles, precision, x, v, m, qm, B, vg, rho, dt,
+                        n_steps, n_sub, x_out, v_out, deposits_out, workspace, ws_bytes,
+                        static_cast<hipStream_t>(hip_stream));
 }
 
 int mhdpic_step(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
@@ -875,12 +1095,12 @@ int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, cons
             if (g) (void)hipGraphDestroy(g);
             return rc;
         }
-        if (e != hipSuccess) return fail(MHDPIC_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return fail_hip("hipStreamEndCapture", e);
         e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
             c->graph_exec = nullptr;
-            return fail(MHDPIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            return fail_hip("hipGraphInstantiate", e);
         }
         c->graph_key = key;  // n_steps is even: the buffers end as they began
     }
@@ -888,29 +1108,6 @@ int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, cons
     return post_error_copy(c, s);
 }
 
-namespace {
-
-std::vector<TileShape> tile_candidates(int ndim, int prec) {
-    std::vector<TileShape> all = ndim == 2
-        ? std::vector<TileShape>{{16, 16, 1}, {32, 16, 1}, {8, 8, 1}, {32, 32, 1}, {64, 16, 1}}
-        : std::vector<TileShape>{{8, 4, 4}, {8, 8, 4}, {4, 4, 4}, {8, 8, 8}, {16, 4, 4}};
-    std::vector<TileShape> ok;
-    for (const TileShape& t : all)
-        if (tile_supported(ndim, prec, t)) ok.push_back(t);
-    return ok;
-}
-
-std::vector<mhdpic_box> with_tile(const mhdpic_box* boxes, int32_t nb, const TileShape& t) {
-    std::vector<mhdpic_box> v(boxes, boxes + nb);
-    for (auto& b : v) {
-        b.tile[0] = t.x;
-        b.tile[1] = t.y;
-        b.tile[2] = b.ndim == 3 ? t.z : 1;
-    }
-    return v;
-}
-
-}  // namespace
 
 int mhdpic_autotune_workspace_size(const mhdpic_box* boxes, int32_t n_boxes,
                                    const int64_t* n_particles, int32_t precision, size_t* bytes) {
@@ -976,12 +1173,9 @@ int mhdpic_deposit_read(mhdpic_ctx* c, int64_t* out, int32_t reset_accumulated, 
     if (!c || !out) return fail(MHDPIC_EINVAL, "ctx or out is NULL");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     c->last_stream = s;
-    const int64_t NC = c->L.NC;
-    const int64_t* nJ = at<int64_t>(c, c->nj == 0 ? c->L.nJ0 : c->L.nJ1);
-    HIP_TRY(hipMemcpyAsync(out, nJ, 4 * NC * 8, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(out + 4 * NC, at<int64_t>(c, c->L.Dcorr), 4 * NC * 8,
-                           hipMemcpyDeviceToDevice, s));
-    if (reset_accumulated) fill_i64(at<int64_t>(c, c->L.Dcorr), 4 * NC, s);
+    int rc = read_deposits(c, out, s);
+    if (rc) return rc;
+    if (reset_accumulated) fill_i64(at<int64_t>(c, c->L.Dcorr), 4 * c->L.NC, s);
     HIP_TRY(hipGetLastError());
     return MHDPIC_OK;
 }
@@ -1005,25 +1199,129 @@ int mhdpic_particles_read(mhdpic_ctx* c, double* x, double* v, void* hip_stream)
     if (!c || !x || !v) return fail(MHDPIC_EINVAL, "ctx, x or v is NULL");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     c->last_stream = s;
+    return read_particles(c, x, v, s);
+}
+
+int mhdpic_counts(mhdpic_ctx* c, int64_t* counts, void* hip_stream) {
+    if (!c || !counts) return fail(MHDPIC_EINVAL, "ctx or counts is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
     const Layout& L = c->L;
-    if (L.N == 0) return MHDPIC_OK;
+    unsigned long long* dc = at<unsigned long long>(c, L.box_count);
+    fill_i64(reinterpret_cast<int64_t*>(dc), c->nb, s);
+    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
+    const unsigned g = grid_for(L.N, 256);
+    if (c->precision == MHDPIC_FP64)
+        hipLaunchKernelGGL(k_box_counts<PartF64>, dim3(g), dim3(256), 0, s, part<PartF64, double>(c, c->cur),
+                           sb, L.N, dc);
+    else
+        hipLaunchKernelGGL(k_box_counts<PartF32>, dim3(g), dim3(256), 0, s, part<PartF32, float>(c, c->cur),
+                           sb, L.N, dc);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(counts, dc, 8 * c->nb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MHDPIC_OK;
+}
+
+int mhdpic_particles_read_ids(mhdpic_ctx* c, double* x, double* v, int32_t* ids, double* tags,
+                              int64_t n_max, int64_t* n_out, void* hip_stream) {
+    if (!c || !n_out || n_max < 0 || (n_max > 0 && (!x || !v || !ids)))
+        return fail(MHDPIC_EINVAL, "ctx, outputs or n_max invalid");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = s;
+    const Layout& L = c->L;
+    uint32_t* dn = at<uint32_t>(c, L.n_out);
+    fill_u32(dn, 1, 0u, s);
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
-    const int64_t* po = at<int64_t>(c, L.part_off);
+    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
+    const unsigned g = grid_for(L.N, 256);
     if (c->precision == MHDPIC_FP64) {
         PartF64 P = part<PartF64, double>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_particles<2, PartF64>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+            hipLaunchKernelGGL((k_read_ids<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
         else
-            hipLaunchKernelGGL((k_read_particles<3, PartF64>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+            hipLaunchKernelGGL((k_read_ids<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
     } else {
         PartF32 P = part<PartF32, float>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_particles<2, PartF32>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+            hipLaunchKernelGGL((k_read_ids<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
         else
-            hipLaunchKernelGGL((k_read_particles<3, PartF32>), dim3(grid_for(L.N, 256)), dim3(256), 0, s, P, x, v, bd, po, c->nb, L.N);
+            hipLaunchKernelGGL((k_read_ids<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
     }
     HIP_TRY(hipGetLastError());
+    uint32_t n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, dn, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_out = n;
+    if ((int64_t)n > n_max) return fail(MHDPIC_ENOMEM, "more particles than n_max; *n_out holds their number");
     return MHDPIC_OK;
+}
+
+int mhdpic_inject(mhdpic_ctx* c, const int64_t* n_new, const double* x, const double* v,
+                  const double* m, const double* qm, const double* tag, void* hip_stream) {
+    if (!c || !n_new) return fail(MHDPIC_EINVAL, "ctx or n_new is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int rc = poll_error(c);
+    if (rc) return rc;
+    c->last_stream = s;
+    const Layout& L = c->L;
+    // offsets of the new particles per box, through a small host buffer
+    constexpr int kChunk = 64;
+    int64_t off[kChunk];
+    int64_t total = 0;
+    for (int b0 = 0; b0 <= c->nb; b0 += kChunk) {
+        const int nc = std::min(kChunk, c->nb + 1 - b0);
+        for (int k = 0; k < nc; ++k) {
+            const int b = b0 + k;
+            off[k] = total;
+            if (b < c->nb) {
+                if (n_new[b] < 0) return fail(MHDPIC_EINVAL, "negative particle count");
+                total += n_new[b];
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(c->ws + L.part_off + 8 * b0, off, 8 * nc, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (total == 0) return MHDPIC_OK;
+    if (!x || !v || !m || !qm) return fail(MHDPIC_EINVAL, "particle arrays are NULL");
+    uint32_t n_cur = 0;
+    HIP_TRY(hipMemcpyAsync(&n_cur, c->ws + L.start + 4 * (size_t)L.NT, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((int64_t)n_cur + total > L.N)
+        return fail(MHDPIC_ENOMEM, "the context's particle slots (the boxes' capacity) are full");
+    if ((int64_t)c->next_id + total >= ((int64_t)1 << 31)) return fail(MHDPIC_ERANGE, "particle ids exhausted");
+    launch_convert(c, s, x, v, m, qm, tag, total, n_cur, c->next_id);
+    c->next_id += (int32_t)total;
+    rc = launch_sort_any(c, s, (int64_t)n_cur + total, n_cur);
+    if (!rc) rc = relaunch_nJ(c, s);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return read_error_now(c, s);
+}
+
+int mhdpic_remove_tagged(mhdpic_ctx* c, double t_cut, double t_now, void* hip_stream) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    if (!c->L.tagged) return fail(MHDPIC_EINVAL, "the context has no particle tags (no capacity was given)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int rc = poll_error(c);
+    if (rc) return rc;
+    c->last_stream = s;
+    const Layout& L = c->L;
+    const unsigned g = grid_for(L.N, 256);
+    if (c->precision == MHDPIC_FP64)
+        hipLaunchKernelGGL(k_mark_tagged<PartF64>, dim3(g), dim3(256), 0, s, part<PartF64, double>(c, c->cur),
+                           at<uint32_t>(c, L.start), L.NT, L.N, t_cut, t_now);
+    else
+        hipLaunchKernelGGL(k_mark_tagged<PartF32>, dim3(g), dim3(256), 0, s, part<PartF32, float>(c, c->cur),
+                           at<uint32_t>(c, L.start), L.NT, L.N, t_cut, t_now);
+    uint32_t n_cur = 0;
+    HIP_TRY(hipMemcpyAsync(&n_cur, c->ws + L.start + 4 * (size_t)L.NT, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rc = launch_sort_any(c, s, n_cur, n_cur);
+    if (!rc) rc = relaunch_nJ(c, s);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return read_error_now(c, s);
 }
 
 int mhdpic_check(mhdpic_ctx* c, void* hip_stream) {

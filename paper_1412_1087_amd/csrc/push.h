@@ -45,7 +45,7 @@ struct Geo {
     static constexpr int NFF = NP - 2 * FOFF;
     static constexpr int CORNER = NDIM == 3 ? PX * PY + PX + 1 : PX + 1;
     static constexpr size_t lds_bytes() {
-        return (size_t)NFF * 4 * 8 + (size_t)NP * 4 * 8 + (size_t)NFF * 6 * sizeof(R);
+        return (size_t)NFF * 4 * 8 + (size_t)NP * 4 * 8 + (size_t)NFF * 6 * sizeof(R) + (size_t)NP * 4;
     }
     // index of tile-local cell (lx, ly, lz), each in [-2, extent + 2)
     __device__ static __forceinline__ int index(int lx, int ly, int lz) {
@@ -61,16 +61,23 @@ struct Geo {
 // Adds 4 channel amounts V[0..3] of one particle to an LDS box [4][NB] whose
 // (-1,-1,-1) stencil corner is at index `base`; weights in the working
 // precision, quantised against the binary64 amounts.
+//
+// A stencil cell k other than the centre is sent the bit pattern of
+// fma(W_k, V, 1.5*2^52), which is 1.5*2^52 with round-half-even(W_k V) added
+// to its low bits, as an integer: the pattern P of 1.5*2^52 plus the rounded
+// product.  The centre is sent round(V) minus the sum of those patterns, that
+// is its own amount minus (K-1) P, for K stencil cells.  A cell of the box
+// thus holds its amount plus P times (the particles whose stencil covers it
+// minus K times those centred on it); the flush removes that from counts of
+// particles per centre cell (kept in `ncnt`, see flush_fix).  This saves the
+// subtraction of P from every contribution.
 template <class Pol, int NDIM, int SX, int SY, int NB>
 __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
                                              const typename Pol::R wx[3],
                                              const typename Pol::R wy[3],
                                              const typename Pol::R wz[3], const double V[4]) {
     using R = typename Pol::R;
-    int64_t acc[4] = {0, 0, 0, 0};
-    int64_t tot[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tot[c] = quant1(V[c]);
+    uint64_t acc[4] = {0, 0, 0, 0};
     unsigned long long* p0 = box + base;
     constexpr int ZN = NDIM == 3 ? 3 : 1;
 #pragma unroll 1
@@ -86,12 +93,9 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
                 unsigned long long* p = p0 + (oz * SY + oy) * SX + ox;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    int64_t q = quant(W, V[c]);
-                    // keep q opaque: otherwise the compiler sums the raw fma
-                    // bits and keeps a second copy of every q for the atomic
-                    asm("" : "+v"(q));
-                    acc[c] += q;
-                    atomicAdd(p + c * NB, (unsigned long long)q);
+                    const uint64_t r = (uint64_t)__double_as_longlong(__builtin_fma(W, V[c], kMagic));
+                    acc[c] += r;
+                    atomicAdd(p + c * NB, (unsigned long long)r);
                 }
             }
         }
@@ -99,7 +103,41 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
     constexpr int CZ = NDIM == 3 ? 1 : 0;
     unsigned long long* pc = p0 + (CZ * SY + 1) * SX + 1;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) atomicAdd(pc + c * NB, (unsigned long long)(tot[c] - acc[c]));
+    for (int c = 0; c < 4; ++c) atomicAdd(pc + c * NB, (unsigned long long)((uint64_t)quant1(V[c]) - acc[c]));
+}
+
+// Pattern excess of an LDS cell at tile-local (lx, ly, lz): P times (the
+// particles whose stencil covers it minus K times those centred on it), from
+// the centre counts of the box (ncnt: corrector counts in the low 16 bits,
+// predictor counts in the high 16 bits; shift selects one).  Counts are only
+// ever nonzero on cells [-1, s] per axis (centres lie in the tile or, for the
+// predictor, one cell beyond it), so only those neighbours are read.  Products
+// are modulo 2^64 like the sums they correct; only a count modulo 2^16
+// matters, because P is a multiple of 2^48.
+template <int NDIM, int PX, int PY>
+__device__ __forceinline__ uint64_t flush_fix(const uint32_t* ncnt, int lx, int ly, int lz, int sx,
+                                              int sy, int sz, int shift) {
+    constexpr int K = NDIM == 3 ? 27 : 9;
+    uint32_t cover = 0, own = 0;
+    const int zlo = NDIM == 3 ? -1 : 0, zhi = NDIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        const int z = lz + dz;
+        if (NDIM == 3 && (z < -1 || z > sz)) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = ly + dy;
+            if (y < -1 || y > sy) continue;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = lx + dx;
+                if (x < -1 || x > sx) continue;
+                const int idx = NDIM == 3 ? ((z + 2) * PY + (y + 2)) * PX + (x + 2) : (y + 2) * PX + (x + 2);
+                const uint32_t n = (ncnt[idx] >> shift) & 0xFFFFu;
+                cover += n;
+                if (dx == 0 && dy == 0 && dz == 0) own = n;
+            }
+        }
+    }
+    return (uint64_t)(cover - (uint32_t)K * own) * ((uint64_t)kMagicHi << 32);
 }
 
 // One particle's stored state (in 2D the third offset reads as 0).
@@ -122,14 +160,28 @@ struct PartRec {
     }
 };
 
+// Launch shape of the push per precision and dimension: threads per block,
+// the waves per SIMD the register budget must allow (4: at most 128 VGPRs),
+// whether the next particle's state is loaded during the current push, and
+// whether the gather reads a stencil row (3 cells) or a plane (9 cells) of
+// fields into registers before its multiply-adds.
+template <class Pol, int NDIM>
+struct PushShape {
+    static constexpr int BLOCK = 512;
+    static constexpr int WAVES = 4;
+    static constexpr bool PREFETCH = NDIM == 3 && std::is_same<typename Pol::R, float>::value;
+    static constexpr bool ROWS = NDIM == 3 && std::is_same<typename Pol::R, double>::value;
+};
+
 template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
+__global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(PushArgsT<Pol> a) {
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long* Dc = reinterpret_cast<unsigned long long*>(smem);
     unsigned long long* Dp = Dc + (size_t)G::NFF * 4;
     R* F = reinterpret_cast<R*>(Dp + (size_t)G::NP * 4);
+    uint32_t* ncnt = reinterpret_cast<uint32_t*>(F + (size_t)G::NFF * 6);  // [NP] centre counts
     constexpr int K = Codes<NDIM>::K;
     __shared__ uint32_t s_cnt[K];
 
@@ -162,6 +214,7 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     const bool do_pred = a.do_pred != 0;
     if (do_pred)
         for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
+    for (int c = threadIdx.x; c < G::NP; c += BLOCK) ncnt[c] = 0u;
     __syncthreads();
 
     const double C = bx.C, C2 = bx.C2, iC = bx.iC, S = bx.S, hdt = bx.hdt;
@@ -169,11 +222,10 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
     const int3 T = make_int3(TX, TY, TZ);
     uint32_t errbits = 0;
 
-    // In 3D the next particle is loaded while this one is pushed: binary64
-    // runs two waves per SIMD (LDS-limited), so registers are free, and the
-    // binary32 kernel still fits the 128 registers of four waves per SIMD.
-    // In 2D the registers are not there.
-    constexpr bool kPrefetch = NDIM == 3;
+    // the binary32 3D kernel loads the next particle while it pushes this one
+    // and still fits the 128 registers of four waves per SIMD; the others
+    // have no registers to spare for it
+    constexpr bool kPrefetch = PushShape<Pol, NDIM>::PREFETCH;
     PartRec<NDIM, R> nxt;
     if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.P, w.begin + (int)threadIdx.x);
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
@@ -191,15 +243,15 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         const double m = (double)cur.m, qm = (double)cur.qm;
 
         typename Pol::K k0 = Pol::kin(v, C, C2, iC);
-        // drift to x^(n+1/2)
-        int s0 = Pol::drift(dl[0], k0.u[0], hx);
-        int s1 = Pol::drift(dl[1], k0.u[1], hy);
-        int s2 = NDIM == 3 ? Pol::drift(dl[2], k0.u[2], hz) : 0;
-        i[0] = wrap_shift(i[0], s0, bx.n[0]);
-        i[1] = wrap_shift(i[1], s1, bx.n[1]);
-        if (NDIM == 3) i[2] = wrap_shift(i[2], s2, bx.n[2]);
+        // drift to x^(n+1/2) (a reflecting face mirrors the particle and its
+        // velocity; the binning has already dropped the particles this drift
+        // takes through an absorbing face)
+        const int s0 = half_drift<Pol>(bx, 0, i[0], dl[0], v[0], k0.u[0], hx);
+        const int s1 = half_drift<Pol>(bx, 1, i[1], dl[1], v[1], k0.u[1], hy);
+        const int s2 = NDIM == 3 ? half_drift<Pol>(bx, 2, i[2], dl[2], v[2], k0.u[2], hz) : 0;
         int lx = i[0] - ox, ly = i[1] - oy, lz = NDIM == 3 ? i[2] - oz : 0;
-        bool inside = lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz;
+        bool inside = lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz &&
+                      s0 != kGone && s1 != kGone && s2 != kGone;
         if (!inside) {
             errbits |= ERRBIT_STATE;
             lx = min(max(lx, 0), sx - 1);
@@ -216,6 +268,33 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         if (NDIM == 3) Pol::weights(dl[2], wz);
         R E[3] = {R(0), R(0), R(0)}, Bp[3] = {R(0), R(0), R(0)};
         constexpr int ZN = NDIM == 3 ? 3 : 1;
+        if (PushShape<Pol, NDIM>::ROWS) {
+            // one stencil row at a time (z outer, then y): 18 values in flight
+#pragma unroll 1
+            for (int r = 0; r < 3 * ZN; ++r) {
+                const int oz2 = r / 3, oy2 = r - 3 * (r / 3);
+                const R* fp = F + fbase + oz2 * G::PY * G::PX + oy2 * G::PX;
+                R fv[3][6];
+#pragma unroll
+                for (int c3 = 0; c3 < 3; ++c3)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) fv[c3][q] = fp[c3 + q * G::NFF];
+                const R wyo = oy2 == 0 ? wy[0] : (oy2 == 1 ? wy[1] : wy[2]);
+                const R wzo = oz2 == 0 ? wz[0] : (oz2 == 1 ? wz[1] : wz[2]);
+#pragma unroll
+                for (int ox2 = 0; ox2 < 3; ++ox2) {
+                    R wxy = wx[ox2] * wyo;
+                    R W = NDIM == 3 ? wxy * wzo : wxy;
+                    const R* f = fv[ox2];
+                    E[0] = Pol::fma(W, f[0], E[0]);
+                    E[1] = Pol::fma(W, f[1], E[1]);
+                    E[2] = Pol::fma(W, f[2], E[2]);
+                    Bp[0] = Pol::fma(W, f[3], Bp[0]);
+                    Bp[1] = Pol::fma(W, f[4], Bp[1]);
+                    Bp[2] = Pol::fma(W, f[5], Bp[2]);
+                }
+            }
+        } else
 #pragma unroll 1
         for (int oz2 = 0; oz2 < ZN; ++oz2) {
             // all 9 x 6 values of the plane first, so the reads overlap
@@ -245,33 +324,41 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
 
         // kick - rotate - kick
         R vn[3];
-        Pol::push(v, E, Bp, qm * hdt, C, C2, vn);
+        typename Pol::Inc inc;
+        Pol::push(v, E, Bp, qm * hdt, C, C2, vn, inc);
         if (!isfinite(vn[0]) || !isfinite(vn[1]) || !isfinite(vn[2])) errbits |= ERRBIT_NONFINITE;
         typename Pol::K k1 = Pol::kin(vn, C, C2, iC);
 
         // corrector feedback at x^(n+1/2): -dM, -dE_k (App. A.3)
+        double dv[3], dek;
+        Pol::corrector(v, vn, k0, k1, inc, dv, dek);
         double Vc[4];
-        Vc[0] = (-(m * ((double)vn[0] - (double)v[0]))) * S;
-        Vc[1] = (-(m * ((double)vn[1] - (double)v[1]))) * S;
-        Vc[2] = (-(m * ((double)vn[2] - (double)v[2]))) * S;
-        Vc[3] = (-(m * (k1.ek - k0.ek))) * S;
+        Vc[0] = (-(m * dv[0])) * S;
+        Vc[1] = (-(m * dv[1])) * S;
+        Vc[2] = (-(m * dv[2])) * S;
+        Vc[3] = (-(m * dek)) * S;
         bool okc = fabs(Vc[0]) < kMaxAmount && fabs(Vc[1]) < kMaxAmount &&
                    fabs(Vc[2]) < kMaxAmount && fabs(Vc[3]) < kMaxAmount;
-        if (okc) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NFF>(Dc, fbase, wx, wy, wz, Vc);
-        else errbits |= ERRBIT_RANGE;
+        if (okc) {
+            lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NFF>(Dc, fbase, wx, wy, wz, Vc);
+            atomicAdd(&ncnt[corner + G::CORNER], 1u);
+        } else {
+            errbits |= ERRBIT_RANGE;
+        }
 
-        // drift to x^(n+1)
-        int t0 = Pol::drift(dl[0], k1.u[0], hx);
-        int t1 = Pol::drift(dl[1], k1.u[1], hy);
-        int t2 = NDIM == 3 ? Pol::drift(dl[2], k1.u[2], hz) : 0;
-        i[0] = wrap_shift(i[0], t0, bx.n[0]);
-        i[1] = wrap_shift(i[1], t1, bx.n[1]);
-        if (NDIM == 3) i[2] = wrap_shift(i[2], t2, bx.n[2]);
+        // drift to x^(n+1); through an absorbing face the particle leaves
+        // after its corrector deposit and before its predictor one
+        int t0 = half_drift<Pol>(bx, 0, i[0], dl[0], vn[0], k1.u[0], hx);
+        int t1 = t0 == kGone ? 0 : half_drift<Pol>(bx, 1, i[1], dl[1], vn[1], k1.u[1], hy);
+        int t2 = NDIM == 3 && t0 != kGone && t1 != kGone
+                     ? half_drift<Pol>(bx, 2, i[2], dl[2], vn[2], k1.u[2], hz) : 0;
+        const bool gone = t0 == kGone || t1 == kGone || t2 == kGone;
+        if (gone) t0 = t1 = t2 = 0;
         const int pbase = corner + (NDIM == 3 ? (t2 * G::PY + t1) * G::PX + t0 : t1 * G::PX + t0);
 
         // n_CR, J_CR at x^(n+1): the predictor input of the next step (at
         // the last sub-step of a sub-cycled step only)
-        if (do_pred) {
+        if (do_pred && !gone) {
             Pol::weights(dl[0], wx);
             Pol::weights(dl[1], wy);
             if (NDIM == 3) Pol::weights(dl[2], wz);
@@ -283,12 +370,16 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
             Vp[3] = (qmm * (double)k1.u[2]) * S;
             bool okp = fabs(Vp[0]) < kMaxAmount && fabs(Vp[1]) < kMaxAmount &&
                        fabs(Vp[2]) < kMaxAmount && fabs(Vp[3]) < kMaxAmount;
-            if (okp) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
-            else errbits |= ERRBIT_RANGE;
+            if (okp) {
+                lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
+                atomicAdd(&ncnt[pbase + G::CORNER], 1u << 16);
+            } else {
+                errbits |= ERRBIT_RANGE;
+            }
         }
 
-        // store x^(n+1), v^(n+1)
-        a.P.cell[j] = pack_cell<NDIM>(i[0], i[1], i[2]);
+        // store x^(n+1), v^(n+1) (a particle that left keeps only its mark)
+        a.P.cell[j] = gone ? kDeadCell : pack_cell<NDIM>(i[0], i[1], i[2]);
         a.P.d[0][j] = dl[0];
         a.P.d[1][j] = dl[1];
         if (NDIM == 3) a.P.d[2][j] = dl[2];
@@ -297,22 +388,14 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         a.P.v[2][j] = vn[2];
 
         // tile and bank residue of the next half-step cell (the operations of
-        // the next step's first drift)
-        int ni[3] = {i[0], i[1], i[2]};
-        R e0 = dl[0], e1 = dl[1], e2 = dl[2];
-        ni[0] = wrap_shift(ni[0], Pol::drift(e0, k1.u[0], hx), bx.n[0]);
-        ni[1] = wrap_shift(ni[1], Pol::drift(e1, k1.u[1], hy), bx.n[1]);
-        if (NDIM == 3) ni[2] = wrap_shift(ni[2], Pol::drift(e2, k1.u[2], hz), bx.n[2]);
-        int res;
-        const int k = move_code<NDIM>(bx, T, tx, ty, tz, ni, errbits, res);
-        // predicted shift of the next predictor deposit (velocity as now)
-        const int p0 = Pol::drift(e0, k1.u[0], hx), p1 = Pol::drift(e1, k1.u[1], hy);
-        const int p2 = NDIM == 3 ? Pol::drift(e2, k1.u[2], hz) : 0;
-        a.code[j] = pack_code(k, res, shift_class<NDIM>(p0, p1, p2));
+        // the next step's first drift), or the gone code if that drift takes
+        // the particle through an absorbing face
+        const int k = next_code<Pol, NDIM>(bx, T, tx, ty, tz, i, dl, vn, k1.u, hx, hy, hz, gone,
+                                            errbits, a.code[j]);
         // most particles stay in the tile: one LDS atomic per wave for them
         const uint64_t stays = __ballot(k == Codes<NDIM>::STAY);
-        if (k != Codes<NDIM>::STAY) atomicAdd(&s_cnt[k], 1u);
-        else if (lane_id() == __ffsll((unsigned long long)stays) - 1)
+        if (k != Codes<NDIM>::STAY && k != Codes<NDIM>::GONE) atomicAdd(&s_cnt[k], 1u);
+        else if (k == Codes<NDIM>::STAY && lane_id() == __ffsll((unsigned long long)stays) - 1)
             atomicAdd(&s_cnt[k], (uint32_t)__popcll(stays));
     }
     if (errbits) latch(a.err, errbits);
@@ -327,9 +410,10 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         bool in = lx >= -1 && lx <= sx && ly >= -1 && ly <= sy && (NDIM == 2 || (lz >= -1 && lz <= sz));
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            unsigned long long val = Dc[q * G::NFF + c];
+            unsigned long long val = Dc[q * G::NFF + c] - fix;
             if (val) atomicAdd((unsigned long long*)&a.Dcorr[q * NC + g], val);
         }
     }
@@ -339,9 +423,10 @@ __global__ void __launch_bounds__(BLOCK) k_push(PushArgsT<Pol> a) {
         bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 16);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            unsigned long long val = Dp[q * G::NP + c];
+            unsigned long long val = Dp[q * G::NP + c] - fix;
             if (val) atomicAdd((unsigned long long*)&a.nJ[q * NC + g], val);
         }
     }
@@ -361,6 +446,7 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
     using R = typename Pol::R;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long* Dp = reinterpret_cast<unsigned long long*>(smem);
+    uint32_t* ncnt = reinterpret_cast<uint32_t*>(Dp + (size_t)G::NP * 4);  // [NP] centre counts
     uint32_t item;
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
@@ -372,6 +458,7 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
     const int sx = tile_extent(bx, 0, tx, TX), sy = tile_extent(bx, 1, ty, TY);
     const int sz = NDIM == 3 ? tile_extent(bx, 2, tz, TZ) : 1;
     for (int c = threadIdx.x; c < G::NP * 4; c += BLOCK) Dp[c] = 0ull;
+    for (int c = threadIdx.x; c < G::NP; c += BLOCK) ncnt[c] = 0u;
     __syncthreads();
     uint32_t errbits = 0;
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
@@ -399,8 +486,12 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         V[3] = (qmm * (double)k.u[2]) * bx.S;
         const bool ok = fabs(V[0]) < kMaxAmount && fabs(V[1]) < kMaxAmount &&
                         fabs(V[2]) < kMaxAmount && fabs(V[3]) < kMaxAmount;
-        if (ok) lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, corner, wx, wy, wz, V);
-        else errbits |= ERRBIT_RANGE;
+        if (ok) {
+            lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, corner, wx, wy, wz, V);
+            atomicAdd(&ncnt[corner + G::CORNER], 1u);
+        } else {
+            errbits |= ERRBIT_RANGE;
+        }
     }
     if (errbits) latch(err, errbits);
     __syncthreads();
@@ -410,9 +501,10 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
+        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            unsigned long long val = Dp[q * G::NP + c];
+            unsigned long long val = Dp[q * G::NP + c] - fix;
             if (val) atomicAdd((unsigned long long*)&nJ[q * NC + g], val);
         }
     }

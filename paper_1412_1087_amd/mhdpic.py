@@ -19,13 +19,15 @@ LIB_PATH = os.environ.get("MHDPIC_LIB") or os.path.join(HERE, "libmhdpic.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
+PERIODIC, REFLECT, ABSORB = 0, 1, 2
 
 EXPORTED = [
     "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
-    "mhdpic_feedback", "mhdpic_step_graph_sub",
+    "mhdpic_feedback", "mhdpic_step_graph_sub", "mhdpic_advance",
+    "mhdpic_particles_read_ids", "mhdpic_counts", "mhdpic_inject", "mhdpic_remove_tagged",
 ]
 
 
@@ -33,7 +35,7 @@ class MhdpicBox(ct.Structure):
     _fields_ = [("ndim", ct.c_int32), ("n", ct.c_int32 * 3), ("dx", ct.c_double * 3),
                 ("x0", ct.c_double * 3), ("C", ct.c_double), ("qomc_gas", ct.c_double),
                 ("hall", ct.c_int32), ("frac_bits", ct.c_int32), ("max_move_cells", ct.c_int32),
-                ("tile", ct.c_int32 * 3)]
+                ("tile", ct.c_int32 * 3), ("boundary", ct.c_int32 * 6), ("capacity", ct.c_int64)]
 
 
 class MhdpicError(RuntimeError):
@@ -73,6 +75,15 @@ def lib():
         L.mhdpic_deposit_read.argtypes = [vp, vp, ct.c_int32, vp]
         L.mhdpic_particles_read.restype = ct.c_int
         L.mhdpic_particles_read.argtypes = [vp, vp, vp, vp]
+        L.mhdpic_particles_read_ids.restype = ct.c_int
+        L.mhdpic_particles_read_ids.argtypes = [vp, vp, vp, vp, vp, ct.c_int64,
+                                                ct.POINTER(ct.c_int64), vp]
+        L.mhdpic_counts.restype = ct.c_int
+        L.mhdpic_counts.argtypes = [vp, ct.POINTER(ct.c_int64), vp]
+        L.mhdpic_inject.restype = ct.c_int
+        L.mhdpic_inject.argtypes = [vp, ct.POINTER(ct.c_int64), vp, vp, vp, vp, vp, vp]
+        L.mhdpic_remove_tagged.restype = ct.c_int
+        L.mhdpic_remove_tagged.argtypes = [vp, ct.c_double, ct.c_double, vp]
         L.mhdpic_check.restype = ct.c_int
         L.mhdpic_check.argtypes = [vp, vp]
         L.mhdpic_destroy.restype = ct.c_int
@@ -94,6 +105,11 @@ def lib():
                                       ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                       ct.POINTER(ct.c_double), ct.c_int32, vp, sz, vp,
                                       ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
+        L.mhdpic_advance.restype = ct.c_int
+        L.mhdpic_advance.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32, ct.POINTER(ct.c_int64),
+                                     ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                     ct.POINTER(ct.c_double), ct.c_int32, ct.c_int32, vp, vp, vp,
+                                     vp, sz, vp]
         L.mhdpic_selftest_arith.restype = ct.c_int
         L.mhdpic_selftest_arith.argtypes = [vp, vp, vp, vp, ct.c_int64, vp]
         _lib = L
@@ -130,6 +146,9 @@ class Box:
     frac_bits: int = 40
     max_move_cells: int = 2
     tile: Sequence[int] = field(default_factory=lambda: (0, 0, 0))
+    # per axis (low, high): PERIODIC, REFLECT or ABSORB
+    boundary: Sequence[Sequence[int]] = ((0, 0), (0, 0), (0, 0))
+    capacity: int = 0  # particle slots for injection (0: the initial count)
 
     def c_struct(self) -> MhdpicBox:
         n = list(self.n) + [1] * (3 - len(self.n))
@@ -147,6 +166,8 @@ class Box:
         b.max_move_cells = int(self.max_move_cells)
         t = list(self.tile) + [0] * (3 - len(self.tile))
         b.tile = (ct.c_int32 * 3)(*t)
+        b.boundary = (ct.c_int32 * 6)(*[int(f) for ax in self.boundary for f in ax])
+        b.capacity = int(self.capacity)
         return b
 
     @property
@@ -246,6 +267,38 @@ class Context:
         _check(lib().mhdpic_particles_read(self._h, _ptr(x), _ptr(v), _stream(stream)))
         return x, v
 
+    def particles_read_ids(self, n_max: int | None = None, stream=None):
+        """Current particles (compacted, any order): x, v [3][n], ids [n] and
+        tags [n] (+inf for particles without one)."""
+        if n_max is None:
+            n_max = sum(self.counts(stream))
+        x = torch.empty((3, max(n_max, 1)), dtype=torch.float64, device=self.device)
+        v = torch.empty_like(x)
+        ids = torch.empty(max(n_max, 1), dtype=torch.int32, device=self.device)
+        tags = torch.empty(max(n_max, 1), dtype=torch.float64, device=self.device)
+        n = ct.c_int64()
+        _check(lib().mhdpic_particles_read_ids(self._h, _ptr(x), _ptr(v), _ptr(ids), _ptr(tags),
+                                               int(n_max), ct.byref(n), _stream(stream)))
+        k = int(n.value)
+        return x[:, :k], v[:, :k], ids[:k], tags[:k]
+
+    def counts(self, stream=None):
+        """Current particles per box."""
+        out = (ct.c_int64 * len(self.boxes))()
+        _check(lib().mhdpic_counts(self._h, out, _stream(stream)))
+        return [int(a) for a in out]
+
+    def inject(self, n_new, x, v, m, qm, tags=None, stream=None):
+        """Adds particles: n_new per box, global positions and four-velocities
+        [3][sum], m, qm (and optional tags) [sum]."""
+        nn = (ct.c_int64 * len(self.boxes))(*[int(a) for a in n_new])
+        _check(lib().mhdpic_inject(self._h, nn, _ptr(x), _ptr(v), _ptr(m), _ptr(qm), _ptr(tags),
+                                   _stream(stream)))
+
+    def remove_tagged(self, t_cut: float, t_now: float, stream=None):
+        """Removes particles with tag < t_cut once t_now >= 2 tag (Sec. 5)."""
+        _check(lib().mhdpic_remove_tagged(self._h, float(t_cut), float(t_now), _stream(stream)))
+
     PHASES = ("bin", "fieldprep", "push", "clear")
 
     def timing(self, enable: bool, phases=None):
@@ -298,6 +351,34 @@ def autotune(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, v
                                  _ptr(ws), int(size.value), _stream(stream), tile, ct.byref(ms)))
     del ws
     return (int(tile[0]), int(tile[1]), int(tile[2])), float(ms.value)
+
+
+def advance(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg, rho, dt,
+            n_steps: int, n_sub: int = 1, precision: int = FP64, workspace=None, stream=None):
+    """One call without a context (mhdpic_advance): returns the final global
+    positions and four-velocities [3][N] and the deposits [8][cells].  The
+    workspace (a uint8 device tensor of at least workspace_size bytes) is
+    allocated here if not given."""
+    arr = _boxes_array(boxes)
+    nps = [int(a) for a in n_particles]
+    npart = (ct.c_int64 * len(boxes))(*nps)
+    N = sum(nps)
+    NC = sum(b.n_cells for b in boxes)
+    dev = x.device
+    if isinstance(dt, (int, float)):
+        dt = [float(dt)] * len(boxes)
+    dts = (ct.c_double * len(boxes))(*[float(a) for a in dt])
+    x_out = torch.empty((3, N), dtype=torch.float64, device=dev)
+    v_out = torch.empty((3, N), dtype=torch.float64, device=dev)
+    D = torch.empty((8, NC), dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = torch.empty(max(workspace_size(boxes, nps, precision), 256), dtype=torch.uint8,
+                                device=dev)
+    _check(lib().mhdpic_advance(arr, len(boxes), npart, int(precision), _ptr(x), _ptr(v), _ptr(m),
+                                _ptr(qm), _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                int(n_sub), _ptr(x_out), _ptr(v_out), _ptr(D), _ptr(workspace),
+                                workspace.numel(), _stream(stream)))
+    return x_out, v_out, D
 
 
 def selftest_arith(a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, stream=None) -> torch.Tensor:

@@ -258,6 +258,112 @@ def shock2d(nx=8192, ny=32, n_particles=16_777_216, seed=3001, C=20.0, n_steps=1
                     dict(seed=seed, band_frac=band_frac))
 
 
+# faces of a box (per axis, low and high): periodic, reflecting, absorbing
+PERIODIC, REFLECT, ABSORB = 0, 1, 2
+
+
+@dataclass
+class ShockSetup:
+    """The shock set-up of Sec. 5 at test size: a conducting (reflecting) wall
+    at x = x0, an inflow (absorbing) face at the far end, periodic in y; the
+    downstream gas at rest with density 4 rho0 behind the shock front x_s,
+    the upstream gas flowing at -v0 toward the wall; B along the shock normal
+    (a parallel shock); CRs injected at the front each step."""
+    box: BoxSpec
+    boundary: tuple
+    B: np.ndarray
+    vg: np.ndarray
+    rho: np.ndarray
+    x_s: float          # shock front
+    v0: float           # upstream flow speed (M_A v_A)
+    v_sh: float         # front speed in the downstream frame, v0/3
+    dt: float
+    eta: float          # injected CR mass per unit swept gas mass
+
+
+def shock_wall2d(nx=96, ny=8, dx=12.0, M_A=30.0, C=None, seed=7001, eta=2e-3,
+                 front_cell=32) -> ShockSetup:
+    """Gas and fields of the shock set-up, with the front at cell front_cell.
+    C defaults to the paper's reduced speed of light 10 sqrt(2) v0 (run
+    R2-REL); dt keeps a particle moving at C within the move limit."""
+    v0 = float(M_A)
+    if C is None:
+        C = 10.0 * np.sqrt(2.0) * v0
+    box = BoxSpec(ndim=2, n=(nx, ny, 1), dx=(dx, dx, 1.0), C=C, hall=0)
+    nc = box.n_cells
+    xc = (np.arange(nx) + 0.5) * dx
+    x_s = front_cell * dx
+    up = np.broadcast_to(xc[None, :] >= x_s, (ny, nx)).ravel()
+    rho = np.where(up, 1.0, 4.0)
+    vg = np.zeros((3, nc))
+    vg[0] = np.where(up, -v0, 0.0)
+    rng = np.random.default_rng(seed)
+    B = np.zeros((3, nc))
+    B[0] = 1.0
+    # a little transverse field, as the Bell modes the shock drives
+    B[1] = 0.05 * rng.normal(size=nc)
+    B[2] = 0.05 * rng.normal(size=nc)
+    dt = 0.9 * 2.0 * dx / C
+    return ShockSetup(box, ((REFLECT, ABSORB), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)),
+                      B, vg, rho, x_s, v0, v0 / 3.0, dt, eta)
+
+
+def shock_injection(setup: ShockSetup, n: int, t: float, seed: int, ppc_up=4.0):
+    """One step's injected CRs (Sec. 5): at the front x_s + v_sh t, uniform
+    in y, isotropic in the frame moving with the front with kinetic energy
+    10 E_sh (E_sh = v0^2/2 per unit mass), boosted to the downstream frame at
+    the reduced speed of light; their total mass is eta times the gas mass the
+    front swept in one step, shared by n particles.  Returns x, v ([3][n]),
+    m, qm ([n]) and the tags (the injection time t)."""
+    rng = np.random.default_rng(seed)
+    box = setup.box
+    C = box.C
+    x = np.zeros((3, n))
+    # within a cell behind the front (the front moves less than a cell a step)
+    front = setup.x_s + setup.v_sh * t
+    x[0] = box.x0[0] + front - rng.uniform(0.0, box.dx[0], size=n)
+    x[1] = box.x0[1] + rng.uniform(0.0, box.n[1] * box.dx[1], size=n)
+    Esh = 0.5 * setup.v0 ** 2
+    g = 1.0 + 10.0 * Esh / (C * C)
+    vmag = C * np.sqrt(g * g - 1.0)
+    v = _isotropic(rng, np.full(n, vmag))
+    b = setup.v_sh / C
+    gb = 1.0 / np.sqrt(1.0 - b * b)
+    vx = gb * (v[0] + b * g * C)
+    v[0] = vx
+    # swept gas: rho0 (v0 + v_sh) per unit area and time, over the box height
+    swept = 1.0 * (setup.v0 + setup.v_sh) * setup.dt * box.n[1] * box.dx[1]
+    m = np.full(n, setup.eta * swept / n)
+    qm = np.ones(n)
+    return (np.ascontiguousarray(x), np.ascontiguousarray(v), m, qm, np.full(n, float(t)))
+
+
+def shock_population(setup: ShockSetup, N: int, seed: int, width_cells: float = 170.0):
+    """CRs accumulated around the front by the time of a run's middle: uniform
+    within width_cells cells on either side of x_s (about 2000 ion inertial
+    lengths at 12 per cell, the CR precursor of Sec. 6), uniform in y,
+    isotropic, with |v| log-uniform between the injection four-velocity
+    (10 E_sh) and 20 times it, each carrying the injected mass of one particle
+    of a 4-per-cell injection.  Returns x, v, m, qm, tags (tag: 0, injected
+    before the run's start)."""
+    rng = np.random.default_rng(seed)
+    box = setup.box
+    C = box.C
+    x = np.zeros((3, N))
+    lo = max(0.0, setup.x_s - width_cells * box.dx[0])
+    hi = min(box.n[0] * box.dx[0], setup.x_s + width_cells * box.dx[0])
+    x[0] = box.x0[0] + rng.uniform(lo, hi, size=N)
+    x[1] = box.x0[1] + rng.uniform(0.0, box.n[1] * box.dx[1], size=N)
+    Esh = 0.5 * setup.v0 ** 2
+    g = 1.0 + 10.0 * Esh / (C * C)
+    v_inj = C * np.sqrt(g * g - 1.0)
+    vmag = v_inj * np.exp(rng.uniform(0.0, np.log(20.0), size=N))
+    v = _isotropic(rng, vmag)
+    # 4 particles per cell at rho0 = 1: each carries eta rho0 dV / 4
+    m = np.full(N, setup.eta * _cell_volume(box) / 4.0)
+    return (np.ascontiguousarray(x), np.ascontiguousarray(v), m, np.ones(N), np.zeros(N))
+
+
 def batch2d(n_boxes=256, seed0=5000, side=(16, 128), ppc=(4, 64), C=20.0, n_steps=100):
     """Independent gyro2d boxes with log-uniform sides and particles per cell."""
     out = []

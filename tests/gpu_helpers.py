@@ -8,17 +8,21 @@ from oracle import oracle as O
 from paper_1412_1087_amd import workloads as W
 
 
-def oracle_box(spec: W.BoxSpec) -> O.Box:
+PERIODIC_FACES = ((0, 0), (0, 0), (0, 0))
+
+
+def oracle_box(spec: W.BoxSpec, boundary=PERIODIC_FACES) -> O.Box:
     return O.Box(ndim=spec.ndim, n=tuple(spec.n), dx=tuple(spec.dx), x0=tuple(spec.x0), C=spec.C,
                  qomc_gas=spec.qomc_gas, hall=spec.hall, frac_bits=spec.frac_bits,
-                 max_move_cells=spec.max_move_cells)
+                 max_move_cells=spec.max_move_cells, bc=tuple(tuple(f) for f in boundary))
 
 
-def gpu_box(spec: W.BoxSpec, tile=(0, 0, 0)):
+def gpu_box(spec: W.BoxSpec, tile=(0, 0, 0), boundary=PERIODIC_FACES, capacity=0):
     from paper_1412_1087_amd import mhdpic as M
     return M.Box(ndim=spec.ndim, n=tuple(spec.n), dx=tuple(spec.dx), x0=tuple(spec.x0), C=spec.C,
                  qomc_gas=spec.qomc_gas, hall=spec.hall, frac_bits=spec.frac_bits,
-                 max_move_cells=spec.max_move_cells, tile=tuple(tile))
+                 max_move_cells=spec.max_move_cells, tile=tuple(tile),
+                 boundary=tuple(tuple(f) for f in boundary), capacity=int(capacity))
 
 
 def to_dev(a: np.ndarray, dev="cuda"):
@@ -72,3 +76,12 @@ class DeviceRun:
 
 def oracle_run(wl: W.Workload) -> O.System:
     return O.System(oracle_box(wl.box), wl.x, wl.v, wl.m, wl.qm)
+
+
+def assert_states_exact(x_g, v_g, x_o, v_o, tag=""):
+    """Binary64 particle states equal the oracle's in every bit, element by
+    element: both sides perform the same operations in the same order."""
+    for name, a, b in (("position", x_g, x_o), ("velocity", v_g, v_o)):
+        bad = np.argwhere(a != b)
+        assert len(bad) == 0, (f"{tag}: {len(bad)} {name} components differ, first (comp, particle) "
+                               f"{tuple(bad[0])}: {a[tuple(bad[0])]!r} vs {b[tuple(bad[0])]!r}")

@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import DeviceRun, oracle_run  # noqa: E402
+from gpu_helpers import DeviceRun, assert_states_exact, oracle_run  # noqa: E402
 
 
 def _need_gpu():
@@ -147,7 +147,7 @@ def test_graph_and_eager_calls_mix_in_one_context():
         (D,) = g.deposits()
         assert (D == o.D).all(), (kind, dt, n)
     ((x, v),) = g.particles()
-    assert np.abs(v - o.v).max() <= 1e-12 * np.abs(o.v).max()
+    assert_states_exact(x, v, o.positions(), o.v, "after graph and eager steps")
 
 
 def test_user_captured_step_replays_match_the_oracle():

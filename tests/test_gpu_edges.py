@@ -9,9 +9,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import DeviceRun, oracle_run  # noqa: E402
-
-REL = 1e-12
+from gpu_helpers import DeviceRun, assert_states_exact, oracle_run  # noqa: E402
 
 
 def _need_gpu():
@@ -24,11 +22,7 @@ def _compare(wl, g, o, tag):
     for ch in range(8):
         assert (D[ch] == o.D[ch]).all(), f"{tag}: channel {ch}"
     ((x, v),) = g.particles()
-    L = np.array([wl.box.n[d] * wl.box.dx[d] for d in range(3)])[:, None]
-    dx = x - o.positions()
-    dx -= L * np.round(dx / L)
-    assert np.abs(dx).max() <= REL * np.abs(L).max(), tag
-    assert np.abs(v - o.v).max() <= REL * max(np.abs(o.v).max(), 1.0), tag
+    assert_states_exact(x, v, o.positions(), o.v, tag)
 
 
 @pytest.mark.parametrize("ndim", [2, 3])

@@ -1,8 +1,10 @@
 """GPU parity: the HIP library against the oracle, through the C ABI.
 
 Deposits must be bit-identical (64-bit fixed point).  Particle states are
-compared element by element; the design target is bit-identical results and
-the bound written in each test is 1e-12 relative (FP64 form).
+compared element by element and must be identical too: both sides perform the
+same binary64 operations in the same order, so a cell index, an offset or a
+velocity component that differs in any bit is a defect (the goal allows
+1e-12 relative; nothing needs it).
 """
 import numpy as np
 import pytest
@@ -15,24 +17,22 @@ from paper_1412_1087_amd import workloads as W  # noqa: E402
 
 from gpu_helpers import DeviceRun, oracle_run, to_dev  # noqa: E402
 
-REL = 1e-12
-
-
 def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
 
 
 def _assert_states(wl, sysO, x_g, v_g):
+    """Positions (read back as x0 + dx((i + 1/2) + d) on both sides) and
+    four-velocities equal the oracle's in every bit, particle by particle."""
     xo = sysO.positions()
     vo = sysO.v
-    L = np.array([wl.box.n[d] * wl.box.dx[d] for d in range(3)])[:, None]
-    dx = x_g - xo
-    dx -= L * np.round(dx / L)
-    scale_x = np.abs(L).max()
-    assert np.abs(dx).max() <= REL * scale_x, np.abs(dx).max()
-    scale_v = np.abs(vo).max()
-    assert np.abs(v_g - vo).max() <= REL * scale_v, np.abs(v_g - vo).max()
+    badx = np.argwhere(x_g != xo)
+    assert len(badx) == 0, (f"{len(badx)} position components differ, first (comp, particle) "
+                            f"{tuple(badx[0])}: {x_g[tuple(badx[0])]!r} vs {xo[tuple(badx[0])]!r}")
+    badv = np.argwhere(v_g != vo)
+    assert len(badv) == 0, (f"{len(badv)} velocity components differ, first (comp, particle) "
+                            f"{tuple(badv[0])}: {v_g[tuple(badv[0])]!r} vs {vo[tuple(badv[0])]!r}")
 
 
 def _parity(wl, n_steps=1, tile=(0, 0, 0), steps_per_call=1):
@@ -271,3 +271,73 @@ def test_parity_dt_changes_between_calls():
         assert (D == o.D).all()
         ((x, v),) = g.particles()
         _assert_states(wl, o, x, v)
+
+
+# ---------------------------------------------------------------------------
+# a lower corner away from zero and a different cell size along each axis
+# ---------------------------------------------------------------------------
+
+X0 = (-3.7, 11.2, 0.5)
+DX = (0.5, 2.0, 1.25)
+
+
+def test_parity_2d_offset_origin_anisotropic_cells():
+    _parity(W.gyro2d(nx=37, ny=23, ppc=5, seed=50, dx=DX, x0=X0), n_steps=4, steps_per_call=2)
+
+
+def test_parity_3d_hall_offset_origin_anisotropic_cells():
+    _parity(W.bell3d(n=(13, 9, 7), ppc=3, seed=51, dx=DX, x0=X0, hall=1), n_steps=3)
+
+
+def test_parity_3d_hall_offset_origin_anisotropic_full_tiles():
+    # several whole 8x4x4 tiles plus ragged ones, Hall term on
+    _parity(W.bell3d(n=(20, 12, 10), ppc=4, seed=52, dx=(1.25, 0.5, 2.0), x0=(7.3, -0.9, -12.6),
+                     hall=1), n_steps=2)
+
+
+def test_parity_multi_box_origins_and_cell_sizes():
+    _need_gpu()
+    wls = [W.gyro2d(nx=17, ny=40, ppc=3, seed=53, dx=(0.5, 2.0, 1.0), x0=(-3.7, 11.2, 0.0)),
+           W.gyro2d(nx=8, ny=8, ppc=11, seed=54, dx=(3.0, 0.75, 1.0), x0=(100.25, -40.5, 0.0)),
+           W.gyro2d(nx=64, ny=16, ppc=2, seed=55)]
+    g = DeviceRun(wls)
+    os_ = [oracle_run(w) for w in wls]
+    for b, o in enumerate(os_):
+        assert (g.deposits()[b] == o.D).all(), f"box {b} init deposit differs"
+    for st in range(3):
+        g.step(1)
+        for w, o in zip(wls, os_):
+            o.step(w.B, w.vg, w.rho, w.dt, 1)
+        Ds = g.deposits()
+        ps = g.particles()
+        for b, (w, o) in enumerate(zip(wls, os_)):
+            assert (Ds[b] == o.D).all(), f"box {b} deposits differ after {st + 1} steps"
+            _assert_states(w, o, *ps[b])
+
+
+def test_parity_3d_multi_box_origins_and_cell_sizes_hall():
+    _need_gpu()
+    wls = [W.bell3d(n=(9, 8, 6), ppc=3, seed=56, dx=DX, x0=X0, hall=1),
+           W.bell3d(n=(6, 10, 5), ppc=2, seed=57, dx=(2.0, 1.0, 0.75), x0=(-50.0, 3.3, 8.125), hall=1)]
+    g = DeviceRun(wls)
+    os_ = [oracle_run(w) for w in wls]
+    for st in range(2):
+        g.step(1)
+        for w, o in zip(wls, os_):
+            o.step(w.B, w.vg, w.rho, w.dt, 1)
+        Ds = g.deposits()
+        ps = g.particles()
+        for b, (w, o) in enumerate(zip(wls, os_)):
+            assert (Ds[b] == o.D).all(), f"box {b} deposits differ after {st + 1} steps"
+            _assert_states(w, o, *ps[b])
+
+
+def test_position_too_far_from_origin_rejected_at_init():
+    _need_gpu()
+    from paper_1412_1087_amd import mhdpic as M
+    wl = W.gyro2d(nx=8, ny=8, ppc=1, seed=58, dx=(0.5, 2.0, 1.0), x0=(-3.7, 11.2, 0.0))
+    wl.x = wl.x.copy()
+    wl.x[0, 7] = -3.7 + 0.5 * 2.0 ** 31 + 1.0
+    with pytest.raises(M.MhdpicError) as e:
+        DeviceRun(wl)
+    assert e.value.code == M.ERANGE

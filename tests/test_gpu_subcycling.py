@@ -3,7 +3,7 @@
 Each step forms E once and moves the particles n_sub times by dt/n_sub;
 -dM, -dE_k accumulate every sub-step and n_CR, J_CR are deposited after the
 last.  Deposits must be bit-identical to the oracle's; particle states are
-compared to 1e-12 relative, like the plain step.
+identical too, like the plain step's.
 """
 import numpy as np
 import pytest
@@ -14,9 +14,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1412_1087_amd import workloads as W  # noqa: E402
 
-from gpu_helpers import DeviceRun, oracle_run  # noqa: E402
-
-REL = 1e-12
+from gpu_helpers import DeviceRun, assert_states_exact, oracle_run  # noqa: E402
 
 
 def _need_gpu():
@@ -30,12 +28,7 @@ def _compare(wl, g, o, tag):
         bad = np.nonzero(D[ch] != o.D[ch])[0]
         assert len(bad) == 0, f"{tag}: channel {ch} differs in {len(bad)} cells"
     ((x, v),) = g.particles()
-    xo, vo = o.positions(), o.v
-    L = np.array([wl.box.n[d] * wl.box.dx[d] for d in range(3)])[:, None]
-    dx = x - xo
-    dx -= L * np.round(dx / L)
-    assert np.abs(dx).max() <= REL * np.abs(L).max(), tag
-    assert np.abs(v - vo).max() <= REL * np.abs(vo).max(), tag
+    assert_states_exact(x, v, o.positions(), o.v, tag)
 
 
 @pytest.mark.parametrize("n_sub", [2, 5])
