@@ -149,6 +149,22 @@ int mhdpic_advance(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_pa
                    const double* dt, int32_t n_steps, int32_t n_sub, double* x_out, double* v_out,
                    int64_t* deposits_out, void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* mhdpic_advance for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments without the workspace, and the same results bit for
+ * bit.  The call's scratch is a static device array of 64 MiB per GPU, held
+ * from the library's first use on that GPU until the process ends; the call
+ * itself calls no allocating routine.  Boxes and particles whose workspace
+ * (mhdpic_workspace_size) exceeds 64 MiB are rejected with MHDPIC_ENOMEM
+ * before any device work.  Every call on one GPU uses the same scratch, so
+ * calls that overlap on one GPU (other threads, other streams) race: the
+ * caller must serialise them.  Waits for the stream. */
+int mhdpic_advance_noalloc(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                           int32_t precision, const double* x, const double* v, const double* m,
+                           const double* qm, const double* B, const double* vg, const double* rho,
+                           const double* dt, int32_t n_steps, int32_t n_sub, double* x_out,
+                           double* v_out, int64_t* deposits_out, void* hip_stream);
+
 /* Advances all particles n_steps steps (App. A.2, A.3) through fixed fields.
  * Waits for the stream only when dt differs from the previous call (the new
  * step constants are uploaded).  The call may be captured into a HIP graph if

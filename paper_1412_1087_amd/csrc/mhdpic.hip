@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -960,6 +961,39 @@ int advance_impl(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* np, in
 
 }  // namespace
 
+// Device scratch of mhdpic_advance_noalloc: the whole workspace of one call
+// (particles, fields, deposits, work lists), so that the call allocates
+// nothing.  Each GPU the library runs on holds its own copy until the process
+// ends.  Host code never uses this name as an address: it looks up each
+// device's copy once with hipGetSymbolAddress and passes that pointer.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch, looked up on the first call on
+// that device, with it current, and kept.
+int scratch_address(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MHDPIC_ENOTSUP, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(MHDPIC_EDEVICE, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MHDPIC_OK;
+}
+
+}  // namespace
+
 namespace {
 
 // n_CR, J_CR of the current particles at their positions, from scratch (after
@@ -1021,6 +1055,31 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
     }
     *out = c;
     return MHDPIC_OK;
+}
+
+int mhdpic_advance_noalloc(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                           int32_t precision, const double* x, const double* v, const double* m,
+                           const double* qm, const double* B, const double* vg, const double* rho,
+                           const double* dt, int32_t n_steps, int32_t n_sub, double* x_out,
+                           double* v_out, int64_t* deposits_out, void* hip_stream) {
+    int ndim;
+    TileShape tile;
+    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
+    if (rc) return rc;
+    const size_t need = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile).total;
+    if (need > kScratchBytes) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "mhdpic_advance_noalloc: these boxes and particles need %zu bytes of scratch; "
+                      "the static scratch holds %zu (use mhdpic_advance with a workspace)",
+                      need, kScratchBytes);
+        return MHDPIC_ENOMEM;
+    }
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    return advance_impl(boxes, n_boxes, n_particles, precision, x, v, m, qm, B, vg, rho, dt,
+                        n_steps, n_sub, x_out, v_out, deposits_out, ws, kScratchBytes,
+                        static_cast<hipStream_t>(hip_stream));
 }
 
 int mhdpic_advance(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,

@@ -26,7 +26,7 @@ EXPORTED = [
     "mhdpic_particles_read", "mhdpic_check", "mhdpic_destroy", "mhdpic_last_error",
     "mhdpic_selftest_arith", "mhdpic_timing_enable", "mhdpic_timing_read",
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
-    "mhdpic_feedback", "mhdpic_step_graph_sub", "mhdpic_advance",
+    "mhdpic_feedback", "mhdpic_step_graph_sub", "mhdpic_advance", "mhdpic_advance_noalloc",
     "mhdpic_particles_read_ids", "mhdpic_counts", "mhdpic_inject", "mhdpic_remove_tagged",
 ]
 
@@ -110,6 +110,11 @@ def lib():
                                      ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                      ct.POINTER(ct.c_double), ct.c_int32, ct.c_int32, vp, vp, vp,
                                      vp, sz, vp]
+        L.mhdpic_advance_noalloc.restype = ct.c_int
+        L.mhdpic_advance_noalloc.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32,
+                                             ct.POINTER(ct.c_int64), ct.c_int32, vp, vp, vp, vp, vp,
+                                             vp, vp, ct.POINTER(ct.c_double), ct.c_int32,
+                                             ct.c_int32, vp, vp, vp, vp]
         L.mhdpic_selftest_arith.restype = ct.c_int
         L.mhdpic_selftest_arith.argtypes = [vp, vp, vp, vp, ct.c_int64, vp]
         _lib = L
@@ -354,11 +359,13 @@ def autotune(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, v
 
 
 def advance(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg, rho, dt,
-            n_steps: int, n_sub: int = 1, precision: int = FP64, workspace=None, stream=None):
+            n_steps: int, n_sub: int = 1, precision: int = FP64, workspace=None, stream=None,
+            noalloc: bool = False):
     """One call without a context (mhdpic_advance): returns the final global
     positions and four-velocities [3][N] and the deposits [8][cells].  The
     workspace (a uint8 device tensor of at least workspace_size bytes) is
-    allocated here if not given."""
+    allocated here if not given.  With noalloc, mhdpic_advance_noalloc runs
+    the same step in the library's static scratch (no workspace)."""
     arr = _boxes_array(boxes)
     nps = [int(a) for a in n_particles]
     npart = (ct.c_int64 * len(boxes))(*nps)
@@ -371,6 +378,12 @@ def advance(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg
     x_out = torch.empty((3, N), dtype=torch.float64, device=dev)
     v_out = torch.empty((3, N), dtype=torch.float64, device=dev)
     D = torch.empty((8, NC), dtype=torch.int64, device=dev)
+    if noalloc:
+        _check(lib().mhdpic_advance_noalloc(arr, len(boxes), npart, int(precision), _ptr(x), _ptr(v),
+                                            _ptr(m), _ptr(qm), _ptr(B), _ptr(vg), _ptr(rho), dts,
+                                            int(n_steps), int(n_sub), _ptr(x_out), _ptr(v_out),
+                                            _ptr(D), _stream(stream)))
+        return x_out, v_out, D
     if workspace is None:
         workspace = torch.empty(max(workspace_size(boxes, nps, precision), 256), dtype=torch.uint8,
                                 device=dev)
