@@ -53,6 +53,31 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     for (int c = threadIdx.x; c < K; c += blockDim.x) cnt[(size_t)item * K + c] = s_cnt[c];
 }
 
+// Codes of a binning in which no particle moves: STAY, or GONE for an empty
+// slot (a particle taken out), with each item's counts.
+template <typename PS, int NDIM>
+__global__ void __launch_bounds__(256)
+k_stay_items(PS P, uint16_t* __restrict__ code, uint32_t* __restrict__ cnt,
+             const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
+    constexpr int K = Codes<NDIM>::K;
+    __shared__ uint32_t s_stay;
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    if (threadIdx.x == 0) s_stay = 0;
+    __syncthreads();
+    uint32_t n = 0;
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
+        const bool live = P.cell[j] != kDeadCell;
+        code[j] = (uint16_t)(live ? Codes<NDIM>::STAY : Codes<NDIM>::GONE);
+        n += live;
+    }
+    atomicAdd(&s_stay, n);
+    __syncthreads();
+    for (int c = threadIdx.x; c < K; c += blockDim.x)
+        cnt[(size_t)item * K + c] = c == Codes<NDIM>::STAY ? s_stay : 0u;
+}
+
 // Source tile of destination tile d for code k.
 template <int NDIM>
 __device__ __forceinline__ int source_tile(const BoxDev& bx, int d, int k) {

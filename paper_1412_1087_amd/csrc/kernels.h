@@ -155,19 +155,6 @@ __global__ void k_init_convert(PS P, const double* __restrict__ x, const double*
     if (P.tag) P.tag[sl] = tag ? tag[j] : (double)INFINITY;
 }
 
-// Marks for removal the particles whose tag is below t_cut once t_now has
-// reached twice their tag (Sec. 5: particles injected before t_cut are
-// removed at twice their injection time).  Slots [0, start[NT]).
-template <typename PS>
-__global__ void k_mark_tagged(PS P, const uint32_t* __restrict__ start, int NT, int64_t cap,
-                              double t_cut, double t_now) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cap || j >= (int64_t)start[NT]) return;
-    if (P.cell[j] == kDeadCell) return;
-    const double t = P.tag[j];
-    if (t < t_cut && 2.0 * t <= t_now) P.cell[j] = kDeadCell;
-}
-
 // ---------------------------------------------------------------------------
 // binning by tile of the half-step cell x^(n+1/2)
 // ---------------------------------------------------------------------------
@@ -265,36 +252,22 @@ __device__ __forceinline__ uint32_t tile_of(const BoxDev& bx, const int3 T, int 
 // Key of a particle that a sort drops (it has left its box).
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 
-// Box of slot j of a sort's source buffer.  Slots below n_old hold particles
-// already grouped by tile (start[t] is tile t's first slot, tile_box[t] its
-// box); slots from n_old on hold new particles, box by box as new_off[]
-// says.  For the first sort of a context n_old is 0 and new_off holds the
-// per-box particle offsets.
+// Box of slot j of a sort's source: slots are filled box by box, off[b] being
+// box b's first (off has nb + 1 entries).
 struct SlotBoxes {
-    const uint32_t* start;
-    const int32_t* tile_box;
-    int NT;
-    int64_t n_old;
-    const int64_t* new_off;
+    const int64_t* off;
     int nb;
-    __device__ __forceinline__ int box(int64_t j) const {
-        if (j >= n_old) return find_box(new_off, nb, j - n_old);
-        int lo = 0, hi = NT - 1;  // last tile whose first slot is <= j
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((int64_t)start[mid] <= j) lo = mid; else hi = mid - 1;
-        }
-        return tile_box[lo];
-    }
+    __device__ __forceinline__ int box(int64_t j) const { return find_box(off, nb, j); }
 };
 
 // Exclusive scan of tile counts and the work list: each tile's particles are
-// split into items of at most P particles.  One block of 1024 threads.
+// split into items of at most P particles; items name slots from base on.
+// One block of 1024 threads.
 __global__ void __launch_bounds__(1024)
 k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
        uint32_t* __restrict__ cursor, const int32_t* __restrict__ tile_box,
        WorkItem* __restrict__ items, uint32_t* __restrict__ item_first,
-       uint32_t* __restrict__ n_items, int NT, int P) {
+       uint32_t* __restrict__ n_items, int NT, int P, uint32_t base) {
     __shared__ uint32_t s_a[1024], s_b[1024];
     const int t = threadIdx.x;
     const int per = (NT + 1023) / 1024;
@@ -326,8 +299,8 @@ k_scan(const uint32_t* __restrict__ count, uint32_t* __restrict__ start,
         for (uint32_t k = 0; k < c; k += (uint32_t)P) {
             WorkItem w;
             w.tile = i;
-            w.begin = (int32_t)(off + k);
-            w.end = (int32_t)(off + min(k + (uint32_t)P, c));
+            w.begin = (int32_t)(base + off + k);
+            w.end = (int32_t)(base + off + min(k + (uint32_t)P, c));
             w.box = tile_box[i];
             items[io++] = w;
         }
@@ -350,6 +323,26 @@ __device__ __forceinline__ void copy_particle(const PS& A, const PS& Bo, int64_t
     Bo.qm[s] = A.qm[j];
     Bo.pid[s] = A.pid[j];
     if (A.tag) Bo.tag[s] = A.tag[j];
+}
+
+// Work list of the current buffer after a sorted tail of new particles was
+// appended: tile t's items are its old items followed by its tail items.
+// The first item of each tile is the sum of the two lists' prefix sums.
+__global__ void k_merge_items(const WorkItem* __restrict__ a, const uint32_t* __restrict__ a_first,
+                              const uint32_t* __restrict__ a_n, const WorkItem* __restrict__ b,
+                              const uint32_t* __restrict__ b_first, const uint32_t* __restrict__ b_n,
+                              WorkItem* __restrict__ out, uint32_t* __restrict__ out_first,
+                              uint32_t* __restrict__ out_n, int NT) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > NT) return;
+    uint32_t o = a_first[t] + b_first[t];
+    out_first[t] = o;
+    if (t == NT) {
+        *out_n = *a_n + *b_n;
+        return;
+    }
+    for (uint32_t k = a_first[t]; k < a_first[t + 1]; ++k) out[o++] = a[k];
+    for (uint32_t k = b_first[t]; k < b_first[t + 1]; ++k) out[o++] = b[k];
 }
 
 // Moves every particle to its slot in the tile-sorted order (dropping those
@@ -609,23 +602,26 @@ __device__ __forceinline__ void slot_position(const PS& P, const BoxDev& bx, int
 }
 
 // Particles in the order of their ids: slot j goes to column pid of the
-// [3][N] outputs (N: the ids given at initialisation).  Slots [0, start[NT]);
-// a particle that has left its box is skipped (its columns keep what the
-// caller filled them with).
+// [3][N] outputs (N: the ids given at initialisation).  One block per work
+// item; a particle that has left its box is skipped (its columns keep what
+// the caller filled them with).
 template <int NDIM, typename PS>
 __global__ void k_read_particles(PS P, double* __restrict__ x, double* __restrict__ v,
-                                 const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t cap,
-                                 int64_t N) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cap || j >= (int64_t)sb.start[sb.NT]) return;
-    if (P.cell[j] == kDeadCell) return;
-    const BoxDev& bx = boxes[sb.box(j)];
-    const int64_t p = P.pid[j];
-    double xx[3];
-    slot_position<NDIM>(P, bx, j, xx);
-    for (int d = 0; d < 3; ++d) {
-        x[d * N + p] = xx[d];
-        v[d * N + p] = (double)P.v[d][j];
+                                 const BoxDev* __restrict__ boxes, const WorkItem* __restrict__ items,
+                                 const uint32_t* __restrict__ n_items, int64_t N) {
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    const BoxDev& bx = boxes[w.box];
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) {
+        if (P.cell[j] == kDeadCell) continue;
+        const int64_t p = P.pid[j];
+        double xx[3];
+        slot_position<NDIM>(P, bx, j, xx);
+        for (int d = 0; d < 3; ++d) {
+            x[d * N + p] = xx[d];
+            v[d * N + p] = (double)P.v[d][j];
+        }
     }
 }
 
@@ -635,37 +631,53 @@ __global__ void k_read_particles(PS P, double* __restrict__ x, double* __restric
 template <int NDIM, typename PS>
 __global__ void k_read_ids(PS P, double* __restrict__ x, double* __restrict__ v,
                            int32_t* __restrict__ ids, double* __restrict__ tags,
-                           const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t cap,
-                           uint32_t* __restrict__ n_out, int64_t n_max) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = j < cap && j < (int64_t)sb.start[sb.NT] && P.cell[j] != kDeadCell;
-    const uint64_t mask = __ballot(live);
-    uint32_t base = 0;
+                           const BoxDev* __restrict__ boxes, const WorkItem* __restrict__ items,
+                           const uint32_t* __restrict__ n_items, uint32_t* __restrict__ n_out,
+                           int64_t n_max) {
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    const BoxDev& bx = boxes[w.box];
     const int lane = lane_id();
-    const int leader = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
-    if (mask && lane == leader) base = atomicAdd(n_out, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (!live) return;
-    const int64_t o = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    if (o >= n_max) return;
-    const BoxDev& bx = boxes[sb.box(j)];
-    double xx[3];
-    slot_position<NDIM>(P, bx, j, xx);
-    for (int d = 0; d < 3; ++d) {
-        x[d * n_max + o] = xx[d];
-        v[d * n_max + o] = (double)P.v[d][j];
+    // the same trip count in every lane of a wave (ballot below)
+    for (int j0 = w.begin; j0 < w.end; j0 += blockDim.x) {
+        const int j = j0 + (int)threadIdx.x;
+        const bool live = j < w.end && P.cell[j] != kDeadCell;
+        const uint64_t mask = __ballot(live);
+        uint32_t base = 0;
+        const int leader = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+        if (mask && lane == leader) base = atomicAdd(n_out, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (!live) continue;
+        const int64_t o = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (o >= n_max) continue;
+        double xx[3];
+        slot_position<NDIM>(P, bx, j, xx);
+        for (int d = 0; d < 3; ++d) {
+            x[d * n_max + o] = xx[d];
+            v[d * n_max + o] = (double)P.v[d][j];
+        }
+        ids[o] = P.pid[j];
+        if (tags) tags[o] = P.tag ? P.tag[j] : (double)INFINITY;
     }
-    ids[o] = P.pid[j];
-    if (tags) tags[o] = P.tag ? P.tag[j] : (double)INFINITY;
 }
 
-// Live particles per box (counts[b], int64, zeroed by the caller).
+// Live particles per box (counts[b], zeroed by the caller).
 template <typename PS>
-__global__ void k_box_counts(PS P, SlotBoxes sb, int64_t cap, unsigned long long* __restrict__ counts) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cap || j >= (int64_t)sb.start[sb.NT]) return;
-    if (P.cell[j] == kDeadCell) return;
-    atomicAdd(&counts[sb.box(j)], 1ull);
+__global__ void k_box_counts(PS P, const WorkItem* __restrict__ items,
+                             const uint32_t* __restrict__ n_items,
+                             unsigned long long* __restrict__ counts) {
+    __shared__ uint32_t s_n;
+    uint32_t item;
+    if (!item_of_block(n_items, item)) return;
+    const WorkItem w = items[item];
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    uint32_t n = 0;
+    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += blockDim.x) n += P.cell[j] != kDeadCell;
+    atomicAdd(&s_n, n);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_n) atomicAdd(&counts[w.box], (unsigned long long)s_n);
 }
 
 __global__ void k_fill_f64(double* p, int64_t n, double val) {

@@ -102,6 +102,8 @@ struct Layout {
     size_t cnt = 0, off = 0;
     int K = 27;
     size_t boxes = 0, part_off = 0, cell_off = 0, box_count = 0, n_out = 0;
+    // a sorted tail of added particles: its tile starts and work list
+    size_t tail_start = 0, tail_items = 0, tail_first = 0, tail_n = 0;
     size_t total = 0;
 };
 
@@ -146,6 +148,7 @@ struct mhdpic_ctx {
     std::vector<hipEvent_t> pool;
     bool dt_uploaded = false;
     int64_t n_init = 0;   // particles given at initialisation (ids 0 .. n_init-1)
+    int64_t tail = 0;     // added particles after the slots the last sort or binning filled
     int32_t next_id = 0;  // id of the next added particle
     // cached graph of mhdpic_step_graph
     hipGraphExec_t graph_exec = nullptr;
@@ -221,7 +224,10 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
         int ntz = ndim == 3 ? (B.n[2] + tile.z - 1) / tile.z : 1;
         L.NT += ntx * nty * ntz;
     }
+    // work items: one per tile and one per 4096 slots, and as many again for a
+    // tail of added particles in contexts with a capacity
     L.NW = L.NT + (int32_t)(L.N / kItemParticles) + 1;
+    if (L.tagged) L.NW = 2 * L.NW;
     const size_t N = (size_t)L.N, NC = (size_t)L.NC;
     const size_t fsz = precision == MHDPIC_FP64 ? 8 : 4;
     // cell, d[ndim], v[3], m, qm (fsz each), pid, tags (binary64, if any)
@@ -259,6 +265,10 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
     L.cell_off = take((size_t)(nb + 1) * 8);
     L.box_count = take((size_t)nb * 8);
     L.n_out = take(4);
+    L.tail_start = take((size_t)(L.NT + 1) * 4);
+    L.tail_items = take((size_t)L.NW * sizeof(WorkItem));
+    L.tail_first = take((size_t)(L.NT + 1) * 4);
+    L.tail_n = take(4);
     L.total = o;
     return L;
 }
@@ -343,11 +353,16 @@ const char* msg_of(uint32_t bits) {
 
 unsigned item_grid(const Layout& L) { return (unsigned)((L.NW + 7) / 8 * 8); }
 
-// Re-bins the particles of the current buffer into the other one.  With
-// rekey, the direction codes are first recomputed for this call's dt;
-// otherwise the push has just written them.
+// Where a binning takes the particles' direction codes from.
+enum BinKeys {
+    kKeysPushed = 0,  // the push has just written them
+    kKeysRekey = 1,   // recomputed for this call's dt
+    kKeysStay = 2,    // none moves: a compaction that drops empty slots
+};
+
+// Re-bins the particles of the current buffer into the other one.
 template <int NDIM, typename PS, typename T>
-int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
+int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
     const Layout& L = c->L;
     const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
     PS A = part<PS, T>(c, c->cur);
@@ -355,10 +370,14 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
     const int it = c->it;
     using Pol = typename std::conditional<std::is_same<PS, PartF64>::value, F64Pol, F32Pol>::type;
-    if (rekey)
+    if (keys == kKeysRekey)
         hipLaunchKernelGGL((k_rekey_items<Pol, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
                            at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
                            at<uint32_t>(c, L.n_items[it]), bd, T3, at<uint32_t>(c, L.err));
+    else if (keys == kKeysStay)
+        hipLaunchKernelGGL((k_stay_items<PS, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
+                           at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
+                           at<uint32_t>(c, L.n_items[it]));
     const unsigned gT = grid_for(L.NT, 4);  // one wave per tile, 4 waves per block
     hipLaunchKernelGGL(k_bin_count<NDIM>, dim3(gT), dim3(256), 0, s, at<uint32_t>(c, L.cnt),
                        at<uint32_t>(c, L.item_first[it]), at<int32_t>(c, L.tile_box), bd,
@@ -381,34 +400,45 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, bool rekey) {
                            at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
     c->cur = 1 - c->cur;
     c->it = 1 - it;
+    c->tail = 0;
     return MHDPIC_OK;
 }
 
-// Box lookup of the slots of the current buffer: its first n_old slots are
-// grouped by tile (the last sort or binning wrote start[]), new particles
-// follow box by box as the part_off table says.
-SlotBoxes slot_boxes(mhdpic_ctx* c, int64_t n_old) {
-    const Layout& L = c->L;
-    return SlotBoxes{at<uint32_t>(c, L.start), at<int32_t>(c, L.tile_box), L.NT, n_old,
-                     at<int64_t>(c, L.part_off), c->nb};
+// Particle arrays of P from slot off on.
+template <typename PS>
+PS shifted(PS P, int64_t off) {
+    P.cell += off;
+    for (int d = 0; d < 3; ++d) {
+        if (P.d[d]) P.d[d] += off;
+        P.v[d] += off;
+    }
+    P.m += off;
+    P.qm += off;
+    P.pid += off;
+    if (P.tag) P.tag += off;
+    return P;
 }
 
-// Sorts the n_src particles of the current buffer by the tile of their cell
-// into the other buffer, dropping those that have left their box, and
-// rebuilds the work list: the first sort of a context (n_old = 0) and the
-// re-sorts after particles are added or removed.
+// Sorts n particles by the tile of their cell (the boxes the part_off table
+// lists, box by box), dropping those that have left their box.
+//   first sort of a context: buffer cur slots [0, n) -> the other buffer,
+//     which becomes current, with the work list rebuilt in list 0;
+//   tail (added particles): the other buffer's slots [slot0, slot0 + n) ->
+//     the current buffer's same slots, with the tail's work list in the
+//     tail arrays (items name slots from slot0 on).
 template <int NDIM, typename PS, typename T>
-int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n_src, int64_t n_old) {
+int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n, int64_t slot0, bool tail) {
     const Layout& L = c->L;
     const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
-    PS A = part<PS, T>(c, c->cur);
-    PS Bo = part<PS, T>(c, 1 - c->cur);
-    const SlotBoxes sb = slot_boxes(c, n_old);
+    const int src = tail ? 1 - c->cur : c->cur, dst = tail ? c->cur : 1 - c->cur;
+    PS A = shifted(part<PS, T>(c, src), slot0);
+    PS Bo = shifted(part<PS, T>(c, dst), slot0);
+    const SlotBoxes sb{at<int64_t>(c, L.part_off), c->nb};
     fill_u32(at<uint32_t>(c, L.count), L.NT, 0u, s);
     // per-block LDS histograms when the tiles fit (up to 128 KB of LDS), else
     // one atomic per distinct tile in each wave
     const bool lds = L.NT <= kSortLdsTiles;
-    const unsigned gC = (unsigned)((n_src + kSortChunk - 1) / kSortChunk);
+    const unsigned gC = (unsigned)((n + kSortChunk - 1) / kSortChunk);
     const size_t hbytes = (size_t)L.NT * sizeof(uint32_t);
     if (lds && hbytes > 65536) {
         HIP_TRY(hipFuncSetAttribute((const void*)k_key_count_lds<NDIM, PS>,
@@ -416,37 +446,41 @@ int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n_src, int64_t n_old) {
         HIP_TRY(hipFuncSetAttribute((const void*)k_scatter_lds<NDIM, PS>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)hbytes));
     }
-    if (n_src > 0 && lds)
+    if (n > 0 && lds)
         hipLaunchKernelGGL((k_key_count_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           sb, n_src, T3, L.NT);
-    else if (n_src > 0)
-        hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(n_src, 256)), dim3(256), 0, s, A,
+                           sb, n, T3, L.NT);
+    else if (n > 0)
+        hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(n, 256)), dim3(256), 0, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           sb, n_src, T3);
-    // the scan rewrites start[]: the box lookup above must have finished
+                           sb, n, T3);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
-                       at<uint32_t>(c, L.start), at<uint32_t>(c, L.cursor), at<int32_t>(c, L.tile_box),
-                       at<WorkItem>(c, L.items[0]), at<uint32_t>(c, L.item_first[0]),
-                       at<uint32_t>(c, L.n_items[0]), L.NT, kItemParticles);
-    if (n_src > 0 && lds)
+                       at<uint32_t>(c, tail ? L.tail_start : L.start), at<uint32_t>(c, L.cursor),
+                       at<int32_t>(c, L.tile_box), at<WorkItem>(c, tail ? L.tail_items : L.items[0]),
+                       at<uint32_t>(c, tail ? L.tail_first : L.item_first[0]),
+                       at<uint32_t>(c, tail ? L.tail_n : L.n_items[0]), L.NT, kItemParticles,
+                       (uint32_t)slot0);
+    if (n > 0 && lds)
         hipLaunchKernelGGL((k_scatter_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A, Bo,
-                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n_src, L.NT);
-    else if (n_src > 0)
-        hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(n_src, 256)), dim3(256), 0, s, A, Bo,
-                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n_src);
-    c->cur = 1 - c->cur;
-    c->it = 0;
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n, L.NT);
+    else if (n > 0)
+        hipLaunchKernelGGL((k_scatter<NDIM, PS>), dim3(grid_for(n, 256)), dim3(256), 0, s, A, Bo,
+                           at<uint32_t>(c, L.key), at<uint32_t>(c, L.cursor), n);
+    if (!tail) {
+        c->cur = 1 - c->cur;
+        c->it = 0;
+        c->tail = 0;
+    }
     return MHDPIC_OK;
 }
 
-int launch_sort_any(mhdpic_ctx* c, hipStream_t s, int64_t n_src, int64_t n_old) {
+int launch_sort_any(mhdpic_ctx* c, hipStream_t s, int64_t n, int64_t slot0, bool tail) {
     if (c->precision == MHDPIC_FP64) {
-        if (c->ndim == 2) return launch_sort<2, PartF64, double>(c, s, n_src, n_old);
-        return launch_sort<3, PartF64, double>(c, s, n_src, n_old);
+        if (c->ndim == 2) return launch_sort<2, PartF64, double>(c, s, n, slot0, tail);
+        return launch_sort<3, PartF64, double>(c, s, n, slot0, tail);
     }
-    if (c->ndim == 2) return launch_sort<2, PartF32, float>(c, s, n_src, n_old);
-    return launch_sort<3, PartF32, float>(c, s, n_src, n_old);
+    if (c->ndim == 2) return launch_sort<2, PartF32, float>(c, s, n, slot0, tail);
+    return launch_sort<3, PartF32, float>(c, s, n, slot0, tail);
 }
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
@@ -482,27 +516,36 @@ int launch_push_t(mhdpic_ctx* c, hipStream_t s, bool p) {
     return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, p);
 }
 
+// What a tiled n_CR, J_CR deposit covers: a work list and, for a removal by
+// tag, the rule's two times.
+struct DepositJob {
+    const WorkItem* items;
+    const uint32_t* n_items;
+    bool remove;
+    double t_cut, t_now;
+};
+
 template <class Pol, int NDIM, int TX, int TY, int TZ>
-int launch_init_deposit_pol(mhdpic_ctx* c, hipStream_t s) {
+int launch_deposit_pol(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
     constexpr int BLOCK = 256;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     const Layout& L = c->L;
     const size_t lds = (size_t)G::NP * 4 * 8 + (size_t)G::NP * 4;
-    auto kern = k_deposit_nJ_tiled<Pol, NDIM, TX, TY, TZ, BLOCK>;
+    auto kern = job.remove ? k_deposit_nJ_tiled<Pol, NDIM, TX, TY, TZ, BLOCK, true>
+                           : k_deposit_nJ_tiled<Pol, NDIM, TX, TY, TZ, BLOCK, false>;
     if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s,
                        part<typename Pol::Part, R>(c, c->cur),
-                       at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1), L.NC,
-                       at<BoxDev>(c, L.boxes), at<WorkItem>(c, L.items[c->it]),
-                       at<uint32_t>(c, L.n_items[c->it]), at<uint32_t>(c, L.err));
+                       at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1), L.NC, at<BoxDev>(c, L.boxes),
+                       job.items, job.n_items, at<uint32_t>(c, L.err), job.t_cut, job.t_now);
     return MHDPIC_OK;
 }
 
 template <int NDIM, int TX, int TY, int TZ>
-int launch_init_deposit_t(mhdpic_ctx* c, hipStream_t s, bool) {
-    if (c->precision == MHDPIC_FP64) return launch_init_deposit_pol<F64Pol, NDIM, TX, TY, TZ>(c, s);
-    return launch_init_deposit_pol<F32Pol, NDIM, TX, TY, TZ>(c, s);
+int launch_deposit_t(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
+    if (c->precision == MHDPIC_FP64) return launch_deposit_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, job);
+    return launch_deposit_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, job);
 }
 
 // Calls F<NDIM, TX, TY, TZ>(c, s, flag) for the context's (compiled) tile.
@@ -525,21 +568,29 @@ int launch_init_deposit_t(mhdpic_ctx* c, hipStream_t s, bool) {
         return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");                   \
     } while (0)
 
+// Adds n_CR, J_CR of the particles of a work list (the current one unless
+// given), or takes back those of the particles a removal by tag picks.
+int launch_deposit(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
+    MHDPIC_TILE_DISPATCH(launch_deposit_t, c, s, job);
+}
+
 int launch_init_deposit(mhdpic_ctx* c, hipStream_t s) {
-    MHDPIC_TILE_DISPATCH(launch_init_deposit_t, c, s, false);
+    const DepositJob job{at<WorkItem>(c, c->L.items[c->it]), at<uint32_t>(c, c->L.n_items[c->it]),
+                         false, 0.0, 0.0};
+    return launch_deposit(c, s, job);
 }
 
 int launch_push(mhdpic_ctx* c, hipStream_t s, bool p) {
     MHDPIC_TILE_DISPATCH(launch_push_t, c, s, p);
 }
 
-int launch_bin_any(mhdpic_ctx* c, hipStream_t s, bool rekey) {
+int launch_bin_any(mhdpic_ctx* c, hipStream_t s, int keys) {
     if (c->precision == MHDPIC_FP64) {
-        if (c->ndim == 2) return launch_bin<2, PartF64, double>(c, s, rekey);
-        return launch_bin<3, PartF64, double>(c, s, rekey);
+        if (c->ndim == 2) return launch_bin<2, PartF64, double>(c, s, keys);
+        return launch_bin<3, PartF64, double>(c, s, keys);
     }
-    if (c->ndim == 2) return launch_bin<2, PartF32, float>(c, s, rekey);
-    return launch_bin<3, PartF32, float>(c, s, rekey);
+    if (c->ndim == 2) return launch_bin<2, PartF32, float>(c, s, keys);
+    return launch_bin<3, PartF32, float>(c, s, keys);
 }
 
 int launch_fieldprep(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
@@ -672,7 +723,7 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
     int rc;
     {
         PhaseTimer t(c, s, 0);
-        rc = launch_bin_any(c, s, true);
+        rc = launch_bin_any(c, s, kKeysRekey);
     }
     for (int st = 0; st < n_steps && !rc; ++st) {
         {
@@ -689,7 +740,7 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
             if (rc) break;
             if (st + 1 < n_steps || !last_sub) {
                 PhaseTimer t(c, s, 0);
-                rc = launch_bin_any(c, s, false);
+                rc = launch_bin_any(c, s, kKeysPushed);
             }
         }
         if (rc) break;
@@ -806,7 +857,7 @@ int read_error_now(mhdpic_ctx* c, hipStream_t s) {
 // pid0 + j.
 void launch_convert(mhdpic_ctx* c, hipStream_t s, const double* x, const double* v,
                     const double* m, const double* qm, const double* tag, int64_t n, int64_t slot0,
-                    int32_t pid0) {
+                    int32_t pid0, int buf) {
     if (n <= 0) return;
     const Layout& L = c->L;
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
@@ -814,7 +865,7 @@ void launch_convert(mhdpic_ctx* c, hipStream_t s, const double* x, const double*
     uint32_t* err = at<uint32_t>(c, L.err);
     const unsigned g = grid_for(n, 256);
     if (c->precision == MHDPIC_FP64) {
-        PartF64 P = part<PartF64, double>(c, c->cur);
+        PartF64 P = part<PartF64, double>(c, buf);
         if (c->ndim == 2)
             hipLaunchKernelGGL((k_init_convert<2, PartF64, double>), dim3(g), dim3(256), 0, s, P, x, v, m,
                                qm, tag, bd, po, c->nb, n, slot0, pid0, err);
@@ -822,7 +873,7 @@ void launch_convert(mhdpic_ctx* c, hipStream_t s, const double* x, const double*
             hipLaunchKernelGGL((k_init_convert<3, PartF64, double>), dim3(g), dim3(256), 0, s, P, x, v, m,
                                qm, tag, bd, po, c->nb, n, slot0, pid0, err);
     } else {
-        PartF32 P = part<PartF32, float>(c, c->cur);
+        PartF32 P = part<PartF32, float>(c, buf);
         if (c->ndim == 2)
             hipLaunchKernelGGL((k_init_convert<2, PartF32, float>), dim3(g), dim3(256), 0, s, P, x, v, m,
                                qm, tag, bd, po, c->nb, n, slot0, pid0, err);
@@ -875,10 +926,10 @@ int init_device(mhdpic_ctx* c, const mhdpic_box* boxes, const int64_t* np, const
     fill_i64(at<int64_t>(c, L.nJ0), 4 * L.NC, s);
     c->cur = 0;
     c->nj = 0;
-    launch_convert(c, s, x, v, m, qm, tag, L.N0, 0, 0);
+    launch_convert(c, s, x, v, m, qm, tag, L.N0, 0, 0, c->cur);
     c->n_init = L.N0;
     c->next_id = (int32_t)L.N0;
-    int rc = launch_sort_any(c, s, L.N0, 0);
+    int rc = launch_sort_any(c, s, L.N0, 0, false);
     if (rc) return rc;
     if (L.N0 > 0) {
         rc = launch_init_deposit(c, s);
@@ -897,25 +948,26 @@ int read_particles(mhdpic_ctx* c, double* x, double* v, hipStream_t s) {
         return fail(MHDPIC_ESTATE, "particles were added: read them with mhdpic_particles_read_ids");
     if (c->n_init == 0) return MHDPIC_OK;
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
-    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
-    const unsigned g = grid_for(L.N, 256);
+    const WorkItem* items = at<WorkItem>(c, L.items[c->it]);
+    const uint32_t* ni = at<uint32_t>(c, L.n_items[c->it]);
+    const unsigned g = item_grid(L);
     const double nan = std::nan("");
     const unsigned gf = (unsigned)std::min<int64_t>(grid_for(3 * c->n_init, 256), 8192);
     hipLaunchKernelGGL(k_fill_f64, dim3(gf), dim3(256), 0, s, x, 3 * c->n_init, nan);
     hipLaunchKernelGGL(k_fill_f64, dim3(gf), dim3(256), 0, s, v, 3 * c->n_init, nan);
-    const int64_t N = c->n_init, cap = L.N;
+    const int64_t N = c->n_init;
     if (c->precision == MHDPIC_FP64) {
         PartF64 P = part<PartF64, double>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_particles<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+            hipLaunchKernelGGL((k_read_particles<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, items, ni, N);
         else
-            hipLaunchKernelGGL((k_read_particles<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+            hipLaunchKernelGGL((k_read_particles<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, bd, items, ni, N);
     } else {
         PartF32 P = part<PartF32, float>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_particles<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+            hipLaunchKernelGGL((k_read_particles<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, items, ni, N);
         else
-            hipLaunchKernelGGL((k_read_particles<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, sb, cap, N);
+            hipLaunchKernelGGL((k_read_particles<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, bd, items, ni, N);
     }
     HIP_TRY(hipGetLastError());
     return MHDPIC_OK;
@@ -999,10 +1051,6 @@ namespace {
 // n_CR, J_CR of the current particles at their positions, from scratch (after
 // particles were added or removed: the same integers as adding or taking
 // back each particle's own).
-int relaunch_nJ(mhdpic_ctx* c, hipStream_t s) {
-    fill_i64(at<int64_t>(c, c->nj == 0 ? c->L.nJ0 : c->L.nJ1), 4 * c->L.NC, s);
-    return launch_init_deposit(c, s);
-}
 
 }  // namespace
 
@@ -1164,6 +1212,7 @@ int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, cons
         c->graph_key = key;  // n_steps is even: the buffers end as they began
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+    if (n_steps > 0) c->tail = 0;  // its binnings took in any added particles
     return post_error_copy(c, s);
 }
 
@@ -1268,14 +1317,14 @@ int mhdpic_counts(mhdpic_ctx* c, int64_t* counts, void* hip_stream) {
     const Layout& L = c->L;
     unsigned long long* dc = at<unsigned long long>(c, L.box_count);
     fill_i64(reinterpret_cast<int64_t*>(dc), c->nb, s);
-    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
-    const unsigned g = grid_for(L.N, 256);
+    const WorkItem* items = at<WorkItem>(c, L.items[c->it]);
+    const uint32_t* ni = at<uint32_t>(c, L.n_items[c->it]);
     if (c->precision == MHDPIC_FP64)
-        hipLaunchKernelGGL(k_box_counts<PartF64>, dim3(g), dim3(256), 0, s, part<PartF64, double>(c, c->cur),
-                           sb, L.N, dc);
+        hipLaunchKernelGGL(k_box_counts<PartF64>, dim3(item_grid(L)), dim3(256), 0, s,
+                           part<PartF64, double>(c, c->cur), items, ni, dc);
     else
-        hipLaunchKernelGGL(k_box_counts<PartF32>, dim3(g), dim3(256), 0, s, part<PartF32, float>(c, c->cur),
-                           sb, L.N, dc);
+        hipLaunchKernelGGL(k_box_counts<PartF32>, dim3(item_grid(L)), dim3(256), 0, s,
+                           part<PartF32, float>(c, c->cur), items, ni, dc);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(counts, dc, 8 * c->nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1292,20 +1341,21 @@ int mhdpic_particles_read_ids(mhdpic_ctx* c, double* x, double* v, int32_t* ids,
     uint32_t* dn = at<uint32_t>(c, L.n_out);
     fill_u32(dn, 1, 0u, s);
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
-    const SlotBoxes sb = slot_boxes(c, INT64_MAX);
-    const unsigned g = grid_for(L.N, 256);
+    const WorkItem* items = at<WorkItem>(c, L.items[c->it]);
+    const uint32_t* ni = at<uint32_t>(c, L.n_items[c->it]);
+    const unsigned g = item_grid(L);
     if (c->precision == MHDPIC_FP64) {
         PartF64 P = part<PartF64, double>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_ids<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
+            hipLaunchKernelGGL((k_read_ids<2, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, items, ni, dn, n_max);
         else
-            hipLaunchKernelGGL((k_read_ids<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
+            hipLaunchKernelGGL((k_read_ids<3, PartF64>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, items, ni, dn, n_max);
     } else {
         PartF32 P = part<PartF32, float>(c, c->cur);
         if (c->ndim == 2)
-            hipLaunchKernelGGL((k_read_ids<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
+            hipLaunchKernelGGL((k_read_ids<2, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, items, ni, dn, n_max);
         else
-            hipLaunchKernelGGL((k_read_ids<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, sb, L.N, dn, n_max);
+            hipLaunchKernelGGL((k_read_ids<3, PartF32>), dim3(g), dim3(256), 0, s, P, x, v, ids, tags, bd, items, ni, dn, n_max);
     }
     HIP_TRY(hipGetLastError());
     uint32_t n = 0;
@@ -1343,16 +1393,40 @@ int mhdpic_inject(mhdpic_ctx* c, const int64_t* n_new, const double* x, const do
     }
     if (total == 0) return MHDPIC_OK;
     if (!x || !v || !m || !qm) return fail(MHDPIC_EINVAL, "particle arrays are NULL");
-    uint32_t n_cur = 0;
-    HIP_TRY(hipMemcpyAsync(&n_cur, c->ws + L.start + 4 * (size_t)L.NT, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if ((int64_t)n_cur + total > L.N)
-        return fail(MHDPIC_ENOMEM, "the context's particle slots (the boxes' capacity) are full");
     if ((int64_t)c->next_id + total >= ((int64_t)1 << 31)) return fail(MHDPIC_ERANGE, "particle ids exhausted");
-    launch_convert(c, s, x, v, m, qm, tag, total, n_cur, c->next_id);
+    // room for the tail: slots after the last sorted one, and work items; a
+    // compaction (a binning in which no particle moves) frees the slots of
+    // removed particles and merges earlier tails
+    uint32_t used[2];
+    for (int pass = 0;; ++pass) {
+        HIP_TRY(hipMemcpyAsync(&used[0], c->ws + L.start + 4 * (size_t)L.NT, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&used[1], c->ws + L.n_items[c->it], 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int64_t s0 = (int64_t)used[0] + c->tail;
+        const int64_t items_max = (int64_t)used[1] + std::min<int64_t>(L.NT, total) + total / kItemParticles + 1;
+        if (s0 + total <= L.N && items_max <= L.NW) break;
+        if (pass == 1)
+            return fail(MHDPIC_ENOMEM, "the context's particle slots (the boxes' capacity) are full");
+        rc = launch_bin_any(c, s, kKeysStay);
+        if (rc) return rc;
+    }
+    const int64_t s0 = (int64_t)used[0] + c->tail;
+    launch_convert(c, s, x, v, m, qm, tag, total, s0, c->next_id, 1 - c->cur);
     c->next_id += (int32_t)total;
-    rc = launch_sort_any(c, s, (int64_t)n_cur + total, n_cur);
-    if (!rc) rc = relaunch_nJ(c, s);
+    rc = launch_sort_any(c, s, total, s0, true);
+    if (rc) return rc;
+    const int it = c->it;
+    hipLaunchKernelGGL(k_merge_items, dim3(grid_for(L.NT + 1, 256)), dim3(256), 0, s,
+                       at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.item_first[it]),
+                       at<uint32_t>(c, L.n_items[it]), at<WorkItem>(c, L.tail_items),
+                       at<uint32_t>(c, L.tail_first), at<uint32_t>(c, L.tail_n),
+                       at<WorkItem>(c, L.items[1 - it]), at<uint32_t>(c, L.item_first[1 - it]),
+                       at<uint32_t>(c, L.n_items[1 - it]), L.NT);
+    c->it = 1 - it;
+    c->tail += total;
+    // the new particles' n_CR, J_CR join the deposits of the state
+    const DepositJob job{at<WorkItem>(c, L.tail_items), at<uint32_t>(c, L.tail_n), false, 0.0, 0.0};
+    rc = launch_deposit(c, s, job);
     if (rc) return rc;
     HIP_TRY(hipGetLastError());
     return read_error_now(c, s);
@@ -1366,18 +1440,11 @@ int mhdpic_remove_tagged(mhdpic_ctx* c, double t_cut, double t_now, void* hip_st
     if (rc) return rc;
     c->last_stream = s;
     const Layout& L = c->L;
-    const unsigned g = grid_for(L.N, 256);
-    if (c->precision == MHDPIC_FP64)
-        hipLaunchKernelGGL(k_mark_tagged<PartF64>, dim3(g), dim3(256), 0, s, part<PartF64, double>(c, c->cur),
-                           at<uint32_t>(c, L.start), L.NT, L.N, t_cut, t_now);
-    else
-        hipLaunchKernelGGL(k_mark_tagged<PartF32>, dim3(g), dim3(256), 0, s, part<PartF32, float>(c, c->cur),
-                           at<uint32_t>(c, L.start), L.NT, L.N, t_cut, t_now);
-    uint32_t n_cur = 0;
-    HIP_TRY(hipMemcpyAsync(&n_cur, c->ws + L.start + 4 * (size_t)L.NT, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    rc = launch_sort_any(c, s, n_cur, n_cur);
-    if (!rc) rc = relaunch_nJ(c, s);
+    // the picked particles' n_CR, J_CR are taken back from the deposits of the
+    // state and their slots marked empty; the next binning drops them
+    const DepositJob job{at<WorkItem>(c, L.items[c->it]), at<uint32_t>(c, L.n_items[c->it]), true,
+                         t_cut, t_now};
+    rc = launch_deposit(c, s, job);
     if (rc) return rc;
     HIP_TRY(hipGetLastError());
     return read_error_now(c, s);

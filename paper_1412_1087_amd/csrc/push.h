@@ -433,15 +433,19 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
 }
 
 // n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
-// once at initialisation, on the tile-sorted particles of the first work
-// list: the same LDS box and deposit as the push's predictor, then a flush
-// with 64-bit global atomics.  The integers equal those of a particle-by-
-// particle deposit.
-template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK>
+// added to nJ for the particles of a work list (all particles at
+// initialisation, the new ones after an injection): the same LDS box and
+// deposit as the push's predictor, then a flush with 64-bit global atomics.
+// The integers equal those of a particle-by-particle deposit.  With REMOVE,
+// only the particles whose tag is below t_cut with t_now at least twice the
+// tag (Sec. 5) are taken: their amounts are deposited negated, which takes
+// back exactly the integers they added (round-half-even is odd), and they are
+// marked as gone.
+template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK, bool REMOVE>
 __global__ void __launch_bounds__(BLOCK)
 k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
                    const BoxDev* __restrict__ boxes, const WorkItem* __restrict__ items,
-                   const uint32_t* __restrict__ n_items, uint32_t* err) {
+                   const uint32_t* __restrict__ n_items, uint32_t* err, double t_cut, double t_now) {
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -462,8 +466,15 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
     __syncthreads();
     uint32_t errbits = 0;
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+        const uint32_t cell = P.cell[j];
+        if (cell == kDeadCell) continue;
+        if (REMOVE) {
+            const double t = P.tag[j];
+            if (!(t < t_cut && 2.0 * t <= t_now)) continue;
+            P.cell[j] = kDeadCell;
+        }
         int i[3];
-        unpack_cell<NDIM>(P.cell[j], i[0], i[1], i[2]);
+        unpack_cell<NDIM>(cell, i[0], i[1], i[2]);
         int lx = i[0] - ox, ly = i[1] - oy, lz = NDIM == 3 ? i[2] - oz : 0;
         if (!(lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz)) {
             errbits |= ERRBIT_STATE;
@@ -484,6 +495,8 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         V[1] = (qmm * (double)k.u[0]) * bx.S;
         V[2] = (qmm * (double)k.u[1]) * bx.S;
         V[3] = (qmm * (double)k.u[2]) * bx.S;
+        if (REMOVE)
+            for (int c = 0; c < 4; ++c) V[c] = -V[c];
         const bool ok = fabs(V[0]) < kMaxAmount && fabs(V[1]) < kMaxAmount &&
                         fabs(V[2]) < kMaxAmount && fabs(V[3]) < kMaxAmount;
         if (ok) {

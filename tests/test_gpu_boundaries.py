@@ -146,6 +146,33 @@ def test_shock_injection_and_removal_match_oracle(precision):
     p.check("end")
 
 
+def test_stacked_injections_removal_and_compaction_match_oracle():
+    """Several injections between two steps (each one a sorted tail of its
+    own), a removal whose slots a later injection needs (the library then
+    compacts the store first), and graph-captured steps after injection."""
+    _need_gpu()
+    st = W.shock_wall2d(nx=64, ny=8, front_cell=24)
+    p = Pair(st.box, st.boundary, np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), np.zeros(0),
+             st.B, st.vg, st.rho, capacity=2600)
+    for k in range(3):
+        p.inject(*W.shock_injection(st, 700, 0.1 * k, seed=950 + k))
+    p.check("three stacked tails")
+    p.step(st.dt, 1)
+    p.check("one step after the tails")
+    # early ones out: 2100 live slots -> 1400; 1000 more only fit once the
+    # removed slots are reclaimed
+    assert p.remove_tagged(0.15, 0.5) == 1400
+    p.inject(*W.shock_injection(st, 1000, 0.3, seed=960))
+    p.check("injection into reclaimed slots")
+    p.inject(*W.shock_injection(st, 100, 0.4, seed=961))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p.ctx.step_graph(p.dB, p.dvg, p.drho, st.dt, 2, stream=s)
+    s.synchronize()
+    p.o.step(p.B, p.vg, p.rho, st.dt, 2)
+    p.check("two graph steps after injection")
+
+
 def test_injection_beyond_capacity_is_refused():
     _need_gpu()
     from paper_1412_1087_amd import mhdpic as M
