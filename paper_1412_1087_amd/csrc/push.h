@@ -44,8 +44,11 @@ struct Geo {
     static constexpr int FOFF = NDIM == 3 ? PX * PY : PX;  // skipped leading plane/row
     static constexpr int NFF = NP - 2 * FOFF;
     static constexpr int CORNER = NDIM == 3 ? PX * PY + PX + 1 : PX + 1;
+    // field words per cell: binary64 E, B interleaved (48 B, three 16-byte
+    // units); binary32 E and B in two planes of 16-byte cells (xyz + a pad)
+    static constexpr int FW = sizeof(R) == 8 ? 6 : 8;
     static constexpr size_t lds_bytes() {
-        return (size_t)NFF * 4 * 8 + (size_t)NP * 4 * 8 + (size_t)NFF * 6 * sizeof(R) + (size_t)NP * 4;
+        return (size_t)NFF * 4 * 8 + (size_t)NP * 4 * 8 + (size_t)NFF * FW * sizeof(R) + (size_t)NP * 4;
     }
     // index of tile-local cell (lx, ly, lz), each in [-2, extent + 2)
     __device__ static __forceinline__ int index(int lx, int ly, int lz) {
@@ -140,6 +143,45 @@ __device__ __forceinline__ uint64_t flush_fix(const uint32_t* ncnt, int lx, int 
     return (uint64_t)(cover - (uint32_t)K * own) * ((uint64_t)kMagicHi << 32);
 }
 
+// E, B of LDS field cell c (field-region index).  A 128-bit LDS read of a
+// wave is served 16 lanes at a time, as a 64-bit atomic is, while a 64-bit
+// read is served 32 lanes at a time; with 16-byte cell units the gather's
+// reads see the same bank pattern as the deposit atomics, for which the
+// binning spreads 16 consecutive lanes over distinct cells modulo 16.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int NFF>
+__device__ __forceinline__ void field_cell(const double* F, int c, double f[6]) {
+    const f64x2* p = reinterpret_cast<const f64x2*>(F + 6 * c);
+    const f64x2 a = p[0], b = p[1], d = p[2];
+    f[0] = a.x;
+    f[1] = a.y;
+    f[2] = b.x;
+    f[3] = b.y;
+    f[4] = d.x;
+    f[5] = d.y;
+}
+template <int NFF>
+__device__ __forceinline__ void field_cell(const float* F, int c, float f[6]) {
+    const f32x4 e = reinterpret_cast<const f32x4*>(F)[c];
+    const f32x4 b = reinterpret_cast<const f32x4*>(F + 4 * NFF)[c];
+    f[0] = e.x;
+    f[1] = e.y;
+    f[2] = e.z;
+    f[3] = b.x;
+    f[4] = b.y;
+    f[5] = b.z;
+}
+__device__ __forceinline__ void field_store(double* F, int NFF, int c, const double* s) {
+    for (int q = 0; q < 6; ++q) F[6 * c + q] = s[q];
+}
+__device__ __forceinline__ void field_store(float* F, int NFF, int c, const float* s) {
+    for (int q = 0; q < 3; ++q) {
+        F[4 * c + q] = s[q];
+        F[4 * NFF + 4 * c + q] = s[3 + q];
+    }
+}
+
 // One particle's stored state (in 2D the third offset reads as 0).
 template <int NDIM, typename R>
 struct PartRec {
@@ -181,7 +223,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     unsigned long long* Dc = reinterpret_cast<unsigned long long*>(smem);
     unsigned long long* Dp = Dc + (size_t)G::NFF * 4;
     R* F = reinterpret_cast<R*>(Dp + (size_t)G::NP * 4);
-    uint32_t* ncnt = reinterpret_cast<uint32_t*>(F + (size_t)G::NFF * 6);  // [NP] centre counts
+    uint32_t* ncnt = reinterpret_cast<uint32_t*>(F + (size_t)G::NFF * G::FW);  // [NP] centre counts
     constexpr int K = Codes<NDIM>::K;
     __shared__ uint32_t s_cnt[K];
 
@@ -204,9 +246,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         bool in = lx >= -1 && lx <= sx && ly >= -1 && ly <= sy && (NDIM == 2 || (lz >= -1 && lz <= sz));
         if (in) {
             int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
-            const R* s = a.EB + 6 * g;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) F[q * G::NFF + c] = s[q];
+            field_store(F, G::NFF, c, a.EB + 6 * g);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) Dc[q * G::NFF + c] = 0ull;
@@ -273,12 +313,10 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
 #pragma unroll 1
             for (int r = 0; r < 3 * ZN; ++r) {
                 const int oz2 = r / 3, oy2 = r - 3 * (r / 3);
-                const R* fp = F + fbase + oz2 * G::PY * G::PX + oy2 * G::PX;
+                const int fc = fbase + oz2 * G::PY * G::PX + oy2 * G::PX;
                 R fv[3][6];
 #pragma unroll
-                for (int c3 = 0; c3 < 3; ++c3)
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) fv[c3][q] = fp[c3 + q * G::NFF];
+                for (int c3 = 0; c3 < 3; ++c3) field_cell<G::NFF>(F, fc + c3, fv[c3]);
                 const R wyo = oy2 == 0 ? wy[0] : (oy2 == 1 ? wy[1] : wy[2]);
                 const R wzo = oz2 == 0 ? wz[0] : (oz2 == 1 ? wz[1] : wz[2]);
 #pragma unroll
@@ -299,11 +337,9 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         for (int oz2 = 0; oz2 < ZN; ++oz2) {
             // all 9 x 6 values of the plane first, so the reads overlap
             R fv[9][6];
-            const R* fp = F + fbase + oz2 * G::PY * G::PX;
+            const int fc = fbase + oz2 * G::PY * G::PX;
 #pragma unroll
-            for (int c9 = 0; c9 < 9; ++c9)
-#pragma unroll
-                for (int q = 0; q < 6; ++q) fv[c9][q] = fp[(c9 / 3) * G::PX + c9 % 3 + q * G::NFF];
+            for (int c9 = 0; c9 < 9; ++c9) field_cell<G::NFF>(F, fc + (c9 / 3) * G::PX + c9 % 3, fv[c9]);
 #pragma unroll
             for (int oy2 = 0; oy2 < 3; ++oy2) {
 #pragma unroll
