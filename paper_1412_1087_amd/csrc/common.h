@@ -33,6 +33,54 @@ constexpr int kItemParticles = 4096;  // particles per work item (at most)
 
 // Box descriptor as the kernels see it.  Per-call fields (dt, hdt, hdx) are
 // refreshed by mhdpic_step before its kernels are enqueued.
+// Row and plane strides of a tile's LDS boxes (tile + 2 ghost cells per
+// side).  The push's LDS accesses are served 16 lanes at a time over 16 bank
+// groups, and the bank group of a cell is its box index modulo 16; the binning
+// orders each group of particles (those arriving from one direction, or
+// staying) over those residues.  Particles arriving through a face of the
+// tile fill one layer of cells, so the strides are padded (at most 3 cells
+// per row, 15 per plane) for the layers normal to each axis, and the whole
+// tile, to spread over the 16 residues as evenly as their cell counts allow
+// (the smallest boxes among the best).
+struct LdsStrides {
+    int sx, sp;
+};
+// Largest count of one residue, minus the even share, over the cells
+// s0*i + s1*j + s2*k (0 <= i < n0, 0 <= j < n1, 0 <= k < n2).
+__host__ __device__ constexpr int residue_excess(int n0, int n1, int n2, int s0, int s1, int s2) {
+    int cnt[16] = {};
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) cnt[(s0 * i + s1 * j + s2 * k) % 16]++;
+    int mx = 0;
+    for (int r = 0; r < 16; ++r) mx = cnt[r] > mx ? cnt[r] : mx;
+    return mx - (n0 * n1 * n2 + 15) / 16;
+}
+__host__ __device__ constexpr LdsStrides lds_strides(int tx, int ty, int tz, int ndim) {
+    const int rx = tx + 4, ry = ty + 4;
+    LdsStrides best{rx, rx * ry};
+    int best_score = 1 << 30, best_cells = 1 << 30;
+    for (int px = 0; px < 4; ++px) {
+        for (int pz = 0; pz < (ndim == 3 ? 16 : 1); ++pz) {
+            const int sx = rx + px, sp = sx * ry + pz;
+            int score = 0;
+            if (ndim == 2)
+                score = residue_excess(ty, 1, 1, sx, 0, 0) + residue_excess(tx, 1, 1, 1, 0, 0) +
+                        residue_excess(tx, ty, 1, 1, sx, 0);
+            else
+                score = residue_excess(ty, tz, 1, sx, sp, 0) + residue_excess(tx, tz, 1, 1, sp, 0) +
+                        residue_excess(tx, ty, 1, 1, sx, 0) + residue_excess(tx, ty, tz, 1, sx, sp);
+            const int cells = ndim == 3 ? sp * (tz + 4) : sx * ry;
+            if (score < best_score || (score == best_score && cells < best_cells)) {
+                best_score = score;
+                best_cells = cells;
+                best = LdsStrides{sx, sp};
+            }
+        }
+    }
+    return best;
+}
+
 struct BoxDev {
     int32_t n[3];      // cells per dimension (n[2] = 1 in 2D)
     int32_t nt[3];     // tiles per dimension
@@ -40,6 +88,7 @@ struct BoxDev {
     int32_t hall;
     int32_t small_last[3];  // 1: the last tile starts at n-2 (no 1-cell tiles)
     int32_t face[3][2];     // per axis, low/high: FACE_PERIODIC, FACE_REFLECT, FACE_ABSORB
+    int32_t lds_sx, lds_sp; // row and plane strides (cells) of the tile's LDS boxes
     int32_t pad0;
     int64_t cell_off;  // global index of this box's first cell
     int64_t part_off;  // first particle slot of this box

@@ -416,8 +416,8 @@ __device__ __forceinline__ int move_code(const BoxDev& bx, int3 T, int tx, int t
     }
     const int lx = i[0] - tile_origin(bx, 0, ux, T.x) + 2;
     const int ly = i[1] - tile_origin(bx, 1, uy, T.y) + 2;
-    int idx = ly * (T.x + 4) + lx;
-    if (NDIM == 3) idx += (i[2] - tile_origin(bx, 2, uz, T.z) + 2) * (T.x + 4) * (T.y + 4);
+    int idx = ly * bx.lds_sx + lx;
+    if (NDIM == 3) idx += (i[2] - tile_origin(bx, 2, uz, T.z) + 2) * bx.lds_sp;
     residue = idx & (kResidues - 1);
     return k;
 }

@@ -61,12 +61,13 @@ constexpr size_t kLdsPerCU = 160 * 1024;
 
 // LDS bytes of the push kernel for a tile shape (the kernel's Geo layout).
 size_t push_lds_bytes(int ndim, int prec, const TileShape& t) {
-    size_t PX = t.x + 4, PY = t.y + 4, PZ = ndim == 3 ? t.z + 4 : 1;
-    size_t NP = PX * PY * PZ;
-    size_t FOFF = ndim == 3 ? PX * PY : PX;
+    const LdsStrides st = lds_strides(t.x, t.y, t.z, ndim);
+    size_t NP = ndim == 3 ? (size_t)st.sp * (t.z + 4) : (size_t)st.sx * (t.y + 4);
+    size_t FOFF = ndim == 3 ? st.sp : st.sx;
     size_t NFF = NP - 2 * FOFF;
-    size_t fsz = prec == MHDPIC_FP64 ? 8 : 4;
-    return NFF * 4 * 8 + NP * 4 * 8 + NFF * 6 * fsz + NP * 4;
+    // fields: binary64 6 words per cell, binary32 8 (two 16-byte planes)
+    size_t fbytes = prec == MHDPIC_FP64 ? 6 * 8 : 8 * 4;
+    return NFF * 4 * 8 + NP * 4 * 8 + NFF * fbytes + NP * 4;
 }
 
 bool tile_compiled(int ndim, const TileShape& t) {
@@ -797,6 +798,9 @@ BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int64_t
         d.small_last[k] = (d.nt[k] >= 2 && d.n[k] % T[k] == 1) ? 1 : 0;
     }
     d.tile_off = tile_off;
+    const LdsStrides st = lds_strides(tile.x, tile.y, ndim == 3 ? tile.z : 1, ndim);
+    d.lds_sx = st.sx;
+    d.lds_sp = st.sp;
     for (int k = 0; k < 3; ++k) {
         d.face[k][0] = B.boundary[k][0];
         d.face[k][1] = B.boundary[k][1];

@@ -39,11 +39,13 @@ struct PushArgsT {
 template <class Pol, int NDIM, int TX, int TY, int TZ>
 struct Geo {
     using R = typename Pol::R;
-    static constexpr int PX = TX + 4, PY = TY + 4, PZ = NDIM == 3 ? TZ + 4 : 1;
-    static constexpr int NP = PX * PY * PZ;
-    static constexpr int FOFF = NDIM == 3 ? PX * PY : PX;  // skipped leading plane/row
+    // boxes of (T + 4) cells per axis, rows and planes padded (lds_strides)
+    static constexpr LdsStrides ST = lds_strides(TX, TY, TZ, NDIM);
+    static constexpr int SX = ST.sx, SP = NDIM == 3 ? ST.sp : 0;  // row, plane strides
+    static constexpr int NP = NDIM == 3 ? SP * (TZ + 4) : SX * (TY + 4);
+    static constexpr int FOFF = NDIM == 3 ? SP : SX;  // skipped leading plane/row
     static constexpr int NFF = NP - 2 * FOFF;
-    static constexpr int CORNER = NDIM == 3 ? PX * PY + PX + 1 : PX + 1;
+    static constexpr int CORNER = NDIM == 3 ? SP + SX + 1 : SX + 1;
     // field words per cell: binary64 E, B interleaved (48 B, three 16-byte
     // units); binary32 E and B in two planes of 16-byte cells (xyz + a pad)
     static constexpr int FW = sizeof(R) == 8 ? 6 : 8;
@@ -52,12 +54,14 @@ struct Geo {
     }
     // index of tile-local cell (lx, ly, lz), each in [-2, extent + 2)
     __device__ static __forceinline__ int index(int lx, int ly, int lz) {
-        return NDIM == 3 ? ((lz + 2) * PY + (ly + 2)) * PX + (lx + 2) : (ly + 2) * PX + (lx + 2);
+        return (NDIM == 3 ? (lz + 2) * SP : 0) + (ly + 2) * SX + (lx + 2);
     }
+    // padding cells come out beyond the box (lx >= TX + 2 or ly >= TY + 2)
     __device__ static __forceinline__ void coords(int p, int& lx, int& ly, int& lz) {
-        lx = p % PX - 2;
-        ly = (p / PX) % PY - 2;
-        lz = NDIM == 3 ? p / (PX * PY) - 2 : 0;
+        const int r = NDIM == 3 ? p % SP : p;
+        lx = r % SX - 2;
+        ly = r / SX - 2;
+        lz = NDIM == 3 ? p / SP - 2 : 0;
     }
 };
 
@@ -74,7 +78,7 @@ struct Geo {
 // minus K times those centred on it); the flush removes that from counts of
 // particles per centre cell (kept in `ncnt`, see flush_fix).  This saves the
 // subtraction of P from every contribution.
-template <class Pol, int NDIM, int SX, int SY, int NB>
+template <class Pol, int NDIM, int SX, int SP, int NB>
 __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
                                              const typename Pol::R wx[3],
                                              const typename Pol::R wy[3],
@@ -93,7 +97,7 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
                 if (centre) continue;
                 R wxy = wx[ox] * wy[oy];
                 double W = (double)(NDIM == 3 ? wxy * wz[oz] : wxy);
-                unsigned long long* p = p0 + (oz * SY + oy) * SX + ox;
+                unsigned long long* p = p0 + oz * SP + oy * SX + ox;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const uint64_t r = (uint64_t)__double_as_longlong(__builtin_fma(W, V[c], kMagic));
@@ -104,7 +108,7 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
         }
     }
     constexpr int CZ = NDIM == 3 ? 1 : 0;
-    unsigned long long* pc = p0 + (CZ * SY + 1) * SX + 1;
+    unsigned long long* pc = p0 + CZ * SP + SX + 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c) atomicAdd(pc + c * NB, (unsigned long long)((uint64_t)quant1(V[c]) - acc[c]));
 }
@@ -117,7 +121,7 @@ __device__ __forceinline__ void lds_deposit4(unsigned long long* box, int base,
 // predictor, one cell beyond it), so only those neighbours are read.  Products
 // are modulo 2^64 like the sums they correct; only a count modulo 2^16
 // matters, because P is a multiple of 2^48.
-template <int NDIM, int PX, int PY>
+template <int NDIM, int SX, int SP>
 __device__ __forceinline__ uint64_t flush_fix(const uint32_t* ncnt, int lx, int ly, int lz, int sx,
                                               int sy, int sz, int shift) {
     constexpr int K = NDIM == 3 ? 27 : 9;
@@ -133,7 +137,7 @@ __device__ __forceinline__ uint64_t flush_fix(const uint32_t* ncnt, int lx, int 
             for (int dx = -1; dx <= 1; ++dx) {
                 const int x = lx + dx;
                 if (x < -1 || x > sx) continue;
-                const int idx = NDIM == 3 ? ((z + 2) * PY + (y + 2)) * PX + (x + 2) : (y + 2) * PX + (x + 2);
+                const int idx = (NDIM == 3 ? (z + 2) * SP : 0) + (y + 2) * SX + (x + 2);
                 const uint32_t n = (ncnt[idx] >> shift) & 0xFFFFu;
                 cover += n;
                 if (dx == 0 && dy == 0 && dz == 0) own = n;
@@ -313,7 +317,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
 #pragma unroll 1
             for (int r = 0; r < 3 * ZN; ++r) {
                 const int oz2 = r / 3, oy2 = r - 3 * (r / 3);
-                const int fc = fbase + oz2 * G::PY * G::PX + oy2 * G::PX;
+                const int fc = fbase + oz2 * G::SP + oy2 * G::SX;
                 R fv[3][6];
 #pragma unroll
                 for (int c3 = 0; c3 < 3; ++c3) field_cell<G::NFF>(F, fc + c3, fv[c3]);
@@ -337,9 +341,9 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         for (int oz2 = 0; oz2 < ZN; ++oz2) {
             // all 9 x 6 values of the plane first, so the reads overlap
             R fv[9][6];
-            const int fc = fbase + oz2 * G::PY * G::PX;
+            const int fc = fbase + oz2 * G::SP;
 #pragma unroll
-            for (int c9 = 0; c9 < 9; ++c9) field_cell<G::NFF>(F, fc + (c9 / 3) * G::PX + c9 % 3, fv[c9]);
+            for (int c9 = 0; c9 < 9; ++c9) field_cell<G::NFF>(F, fc + (c9 / 3) * G::SX + c9 % 3, fv[c9]);
 #pragma unroll
             for (int oy2 = 0; oy2 < 3; ++oy2) {
 #pragma unroll
@@ -376,7 +380,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         bool okc = fabs(Vc[0]) < kMaxAmount && fabs(Vc[1]) < kMaxAmount &&
                    fabs(Vc[2]) < kMaxAmount && fabs(Vc[3]) < kMaxAmount;
         if (okc) {
-            lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NFF>(Dc, fbase, wx, wy, wz, Vc);
+            lds_deposit4<Pol, NDIM, G::SX, G::SP, G::NFF>(Dc, fbase, wx, wy, wz, Vc);
             atomicAdd(&ncnt[corner + G::CORNER], 1u);
         } else {
             errbits |= ERRBIT_RANGE;
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
                      ? half_drift<Pol>(bx, 2, i[2], dl[2], vn[2], k1.u[2], hz) : 0;
         const bool gone = t0 == kGone || t1 == kGone || t2 == kGone;
         if (gone) t0 = t1 = t2 = 0;
-        const int pbase = corner + (NDIM == 3 ? (t2 * G::PY + t1) * G::PX + t0 : t1 * G::PX + t0);
+        const int pbase = corner + (NDIM == 3 ? t2 * G::SP : 0) + t1 * G::SX + t0;
 
         // n_CR, J_CR at x^(n+1): the predictor input of the next step (at
         // the last sub-step of a sub-cycled step only)
@@ -407,7 +411,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
             bool okp = fabs(Vp[0]) < kMaxAmount && fabs(Vp[1]) < kMaxAmount &&
                        fabs(Vp[2]) < kMaxAmount && fabs(Vp[3]) < kMaxAmount;
             if (okp) {
-                lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, pbase, wx, wy, wz, Vp);
+                lds_deposit4<Pol, NDIM, G::SX, G::SP, G::NP>(Dp, pbase, wx, wy, wz, Vp);
                 atomicAdd(&ncnt[pbase + G::CORNER], 1u << 16);
             } else {
                 errbits |= ERRBIT_RANGE;
@@ -446,7 +450,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         bool in = lx >= -1 && lx <= sx && ly >= -1 && ly <= sy && (NDIM == 2 || (lz >= -1 && lz <= sz));
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
-        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 0);
+        const uint64_t fix = flush_fix<NDIM, G::SX, G::SP>(ncnt, lx, ly, lz, sx, sy, sz, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             unsigned long long val = Dc[q * G::NFF + c] - fix;
@@ -459,7 +463,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
-        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 16);
+        const uint64_t fix = flush_fix<NDIM, G::SX, G::SP>(ncnt, lx, ly, lz, sx, sy, sz, 16);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             unsigned long long val = Dp[q * G::NP + c] - fix;
@@ -536,7 +540,7 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         const bool ok = fabs(V[0]) < kMaxAmount && fabs(V[1]) < kMaxAmount &&
                         fabs(V[2]) < kMaxAmount && fabs(V[3]) < kMaxAmount;
         if (ok) {
-            lds_deposit4<Pol, NDIM, G::PX, G::PY, G::NP>(Dp, corner, wx, wy, wz, V);
+            lds_deposit4<Pol, NDIM, G::SX, G::SP, G::NP>(Dp, corner, wx, wy, wz, V);
             atomicAdd(&ncnt[corner + G::CORNER], 1u);
         } else {
             errbits |= ERRBIT_RANGE;
@@ -550,7 +554,7 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         bool in = lx < sx + 2 && ly < sy + 2 && (NDIM == 2 || lz < sz + 2);
         if (!in) continue;
         int64_t g = global_cell<NDIM>(bx, ox + lx, oy + ly, oz + lz);
-        const uint64_t fix = flush_fix<NDIM, G::PX, G::PY>(ncnt, lx, ly, lz, sx, sy, sz, 0);
+        const uint64_t fix = flush_fix<NDIM, G::SX, G::SP>(ncnt, lx, ly, lz, sx, sy, sz, 0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             unsigned long long val = Dp[q * G::NP + c] - fix;
