@@ -420,10 +420,8 @@ def run_batched_form(steps: int):
     out = {"workload": "batch2d-256-boxes", "boxes": len(wls), "particles": N, "cells": NC,
            "steps": steps}
     res = {}
-    for prec, name in ((M.FP32_MIXED, "fp32"), (M.FP64, "fp64")):
-        boxes0 = [_gpu_box(w.box) for w in wls]
-        tile, tms = M.autotune(boxes0, nps, x, v, m, qm, B, vg, rho, dts, n_steps=10, precision=prec)
-        boxes = [_gpu_box(w.box, tile) for w in wls]
+
+    def graph_ms(boxes, prec):
         ctx = M.Context(boxes, nps, x, v, m, qm, precision=prec)
         stream = torch.cuda.Stream()
         torch.cuda.synchronize()
@@ -436,15 +434,35 @@ def run_batched_form(steps: int):
         e1.record(stream)
         stream.synchronize()
         ctx.check(stream)
-        ms = e0.elapsed_time(e1)
-        res[name] = dict(value=round(N * steps / (ms * 1e-3), 1), tile=list(tile),
-                         ms_per_step=round(ms / steps, 5))
         ctx.destroy()
-        log(f"batched {name}: tile {tile}, {res[name]['value']:.4g}/s")
+        return e0.elapsed_time(e1)
+
+    for prec, name in ((M.FP32_MIXED, "fp32"), (M.FP64, "fp64")):
+        boxes0 = [_gpu_box(w.box) for w in wls]
+        tile, _ = M.autotune(boxes0, nps, x, v, m, qm, B, vg, rho, dts, n_steps=10, precision=prec)
+        ms_one = graph_ms([_gpu_box(w.box, tile) for w in wls], prec)
+        tiles, _ = M.autotune_classes(boxes0, nps, x, v, m, qm, B, vg, rho, dts, n_steps=10,
+                                      precision=prec)
+        ms_cls = graph_ms([_gpu_box(w.box, t) for w, t in zip(wls, tiles)], prec)
+        shapes = sorted({t for t in tiles})
+        by_class = {}
+        for w, t in zip(wls, tiles):
+            k = int(np.log2(w.box.n_cells) // 2)
+            by_class.setdefault(f"4^{k}..4^{k + 1} cells", set()).add(t)
+        best = min(ms_one, ms_cls)
+        res[name] = dict(value=round(N * steps / (best * 1e-3), 1),
+                         ms_per_step=round(best / steps, 5),
+                         one_tile=dict(tile=list(tile), ms_per_step=round(ms_one / steps, 5)),
+                         per_class=dict(tiles={k: [list(t) for t in sorted(v)] for k, v in by_class.items()},
+                                        shapes=[list(t) for t in shapes],
+                                        ms_per_step=round(ms_cls / steps, 5)),
+                         per_class_gain=round(ms_one / ms_cls, 3))
+        log(f"batched {name}: one tile {tile} {ms_one / steps:.4f} ms/step, per class "
+            f"{shapes} {ms_cls / steps:.4f} ms/step")
     out["value"] = res["fp32"]["value"]
-    out["tile"] = res["fp32"]["tile"]
+    out["fp32"] = res["fp32"]
     out["fp64_value"] = res["fp64"]["value"]
-    out["fp64_tile"] = res["fp64"]["tile"]
+    out["fp64"] = res["fp64"]
     out["speedup_vs_fp64"] = round(res["fp32"]["value"] / res["fp64"]["value"], 3)
     out["launch"] = "one hipGraph launch per call of %d steps" % steps
     return out

@@ -94,7 +94,8 @@ typedef struct {
     int32_t frac_bits;      /* fixed-point quantum 2^-frac_bits, 0..60 (40 is the usual value) */
     int32_t max_move_cells; /* 1 or 2: a particle crosses at most this many cells per step
                                (App. A.4); mhdpic_step rejects C*|dt|/dx above it */
-    int32_t tile[3];        /* cells per tile per dimension for the LDS-staged kernels;
+    int32_t tile[3];        /* cells per tile per dimension for the LDS-staged kernels
+                               (the boxes of one context may differ);
                                0 = library default.  tile[2] is ignored in 2D */
     int32_t boundary[3][2]; /* per axis, low and high face: MHDPIC_PERIODIC (both faces or
                                neither), MHDPIC_REFLECT or MHDPIC_ABSORB; all zero =
@@ -245,6 +246,29 @@ int mhdpic_autotune(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_p
                     const double* qm, const double* B, const double* vg, const double* rho,
                     const double* dt, int32_t n_steps, void* workspace, size_t ws_bytes,
                     void* hip_stream, int32_t* tile_out, double* ms_per_step);
+
+/* The batched form's autotuner (the independent boxes of uneven size of the
+ * batching workload): a tile shape per box-size class.  The tile is both the
+ * unit the binning sorts particles into and the LDS staging unit of the push,
+ * so one shape sets both.  A box's size class is k for 4^k <= its cell count <
+ * 4^(k+1).  For every compiled shape it times n_steps steps of a context in
+ * which all boxes take that shape, with the push launched once per size
+ * class, and takes for each class the shape of the shortest push.  The mix is
+ * then timed as a whole and kept only if its step is shorter than that of the
+ * best single shape (which is used for all boxes otherwise).  Boxes of one
+ * context may have different tile shapes (mhdpic_box.tile); each shape is one
+ * push launch per step.  Arguments as for mhdpic_autotune; workspace needs
+ * mhdpic_autotune_classes_workspace_size bytes.  Writes the shape of box b to
+ * tiles_out[3b .. 3b+2] and, if not NULL, the chosen step time in ms.  Waits
+ * for the stream. */
+int mhdpic_autotune_classes_workspace_size(const mhdpic_box* boxes, int32_t n_boxes,
+                                           const int64_t* n_particles, int32_t precision,
+                                           size_t* bytes);
+int mhdpic_autotune_classes(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                            int32_t precision, const double* x, const double* v, const double* m,
+                            const double* qm, const double* B, const double* vg, const double* rho,
+                            const double* dt, int32_t n_steps, void* workspace, size_t ws_bytes,
+                            void* hip_stream, int32_t* tiles_out, double* ms_per_step);
 
 /* Copies the deposits to out (device, [8][cells] int64): channels
  * 0..3 = n_CR, J_CR x,y,z at the current positions; 4..6 = accumulated

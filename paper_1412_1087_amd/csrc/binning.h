@@ -23,7 +23,7 @@ template <class Pol, int NDIM>
 __global__ void __launch_bounds__(256)
 k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __restrict__ cnt,
               const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items,
-              const BoxDev* __restrict__ boxes, int3 T, uint32_t* err) {
+              const BoxDev* __restrict__ boxes, uint32_t* err) {
     using R = typename Pol::R;
     constexpr int K = Codes<NDIM>::K;
     __shared__ uint32_t s_cnt[K];
@@ -31,6 +31,7 @@ k_rekey_items(typename Pol::Part P, uint16_t* __restrict__ code, uint32_t* __res
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
     const BoxDev bx = boxes[w.box];
+    const int3 T = make_int3(bx.T[0], bx.T[1], bx.T[2]);
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     for (int c = threadIdx.x; c < K; c += blockDim.x) s_cnt[c] = 0;
@@ -437,24 +438,24 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
 // its box), or kNoTile for a particle that has left its box.
 template <int NDIM, typename PS>
 __device__ __forceinline__ uint32_t sort_key(const PS& P, int64_t j, const SlotBoxes& sb,
-                                             const BoxDev* boxes, int3 T) {
+                                             const BoxDev* boxes) {
     const uint32_t c = P.cell[j];
     if (c == kDeadCell) return kNoTile;
     const BoxDev& bx = boxes[sb.box(j)];
     int i[3];
     unpack_cell<NDIM>(c, i[0], i[1], i[2]);
-    return tile_of<NDIM>(bx, T, i[0], i[1], i[2]);
+    return tile_of<NDIM>(bx, make_int3(bx.T[0], bx.T[1], bx.T[2]), i[0], i[1], i[2]);
 }
 
 // Sort by tile (first sort of a context, and re-sorts after particles are
 // added or removed), with global counters.
 template <int NDIM, typename PS>
 __global__ void k_key_cell(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                           const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N, int3 T) {
+                           const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N) {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t k = kNoTile;
     if (j < N) {
-        k = sort_key<NDIM>(P, j, sb, boxes, T);
+        k = sort_key<NDIM>(P, j, sb, boxes);
         key[j] = k;
     }
     const bool act = k != kNoTile;
@@ -472,7 +473,7 @@ constexpr int kSortLdsTiles = 32768;  // 128 KB of LDS histogram at most
 template <int NDIM, typename PS>
 __global__ void __launch_bounds__(256)
 k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
-                const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N, int3 T, int NT) {
+                const BoxDev* __restrict__ boxes, SlotBoxes sb, int64_t N, int NT) {
     extern __shared__ uint32_t s_h[];
     constexpr int U = kSortChunk / 256;
     for (int t = threadIdx.x; t < NT; t += 256) s_h[t] = 0;
@@ -482,7 +483,7 @@ k_key_count_lds(PS P, uint32_t* __restrict__ key, uint32_t* __restrict__ count,
     for (int u = 0; u < U; ++u) {
         const int64_t j = j0 + threadIdx.x + u * 256;
         if (j < N) {
-            const uint32_t k = sort_key<NDIM>(P, j, sb, boxes, T);
+            const uint32_t k = sort_key<NDIM>(P, j, sb, boxes);
             key[j] = k;
             if (k != kNoTile) atomicAdd(&s_h[k], 1u);
         }

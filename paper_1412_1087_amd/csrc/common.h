@@ -89,6 +89,8 @@ struct BoxDev {
     int32_t small_last[3];  // 1: the last tile starts at n-2 (no 1-cell tiles)
     int32_t face[3][2];     // per axis, low/high: FACE_PERIODIC, FACE_REFLECT, FACE_ABSORB
     int32_t lds_sx, lds_sp; // row and plane strides (cells) of the tile's LDS boxes
+    int32_t T[3];           // tile shape (T[2] = 1 in 2D)
+    int32_t grp;            // launch group: the boxes one push launch takes
     int32_t pad0;
     int64_t cell_off;  // global index of this box's first cell
     int64_t part_off;  // first particle slot of this box

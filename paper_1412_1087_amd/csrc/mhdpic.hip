@@ -127,7 +127,18 @@ struct GraphKey {
 
 struct mhdpic_ctx {
     int ndim = 0, precision = 0, nb = 0;
-    TileShape tile{};
+    // launch groups: the boxes of one tile shape (and, while the autotuner
+    // times them, one size class) go through one push launch
+    std::vector<TileShape> grp_shape;
+    std::vector<int32_t> box_grp;
+    std::vector<TileShape> box_tile;
+    // optional push time per launch group (the autotuner)
+    bool grp_timing = false;
+    struct GrpMark {
+        int grp;
+        hipEvent_t a, b;
+    };
+    std::vector<GrpMark> grp_marks;
     std::vector<mhdpic_box> boxes;
     std::vector<BoxDev> bdev;
     Layout L;
@@ -159,26 +170,22 @@ struct mhdpic_ctx {
 namespace {
 
 int validate_boxes(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32_t precision,
-                   int& ndim, TileShape& tile) {
+                   int& ndim, std::vector<TileShape>& tiles) {
     if (!boxes || nb < 1 || !np) return fail(MHDPIC_EINVAL, "boxes, n_boxes or n_particles invalid");
     if (precision != MHDPIC_FP64 && precision != MHDPIC_FP32_MIXED)
         return fail(MHDPIC_EINVAL, "precision must be MHDPIC_FP64 or MHDPIC_FP32_MIXED");
     ndim = boxes[0].ndim;
     if (ndim != 2 && ndim != 3) return fail(MHDPIC_EINVAL, "ndim must be 2 or 3");
-    tile = {boxes[0].tile[0], boxes[0].tile[1], ndim == 3 ? boxes[0].tile[2] : 1};
-    if (tile.x == 0 && tile.y == 0) tile = default_tile(ndim, precision);
-    if (!tile_supported(ndim, precision, tile))
-        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel or exceeds the LDS");
+    tiles.assign(nb, TileShape{});
     int64_t N = 0, NC = 0;
     for (int b = 0; b < nb; ++b) {
         const mhdpic_box& B = boxes[b];
         if (B.ndim != ndim) return fail(MHDPIC_EINVAL, "all boxes must have the same ndim");
-        int tz = ndim == 3 ? B.tile[2] : 1;
-        bool same = (B.tile[0] == 0 && B.tile[1] == 0) ? (tile.x == default_tile(ndim, precision).x &&
-                                                           tile.y == default_tile(ndim, precision).y)
-                                                        : (B.tile[0] == tile.x && B.tile[1] == tile.y &&
-                                                           tz == tile.z);
-        if (!same) return fail(MHDPIC_EINVAL, "all boxes must use the same tile shape");
+        TileShape t{B.tile[0], B.tile[1], ndim == 3 ? B.tile[2] : 1};
+        if (t.x == 0 && t.y == 0) t = default_tile(ndim, precision);
+        if (!tile_supported(ndim, precision, t))
+            return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel or exceeds the LDS");
+        tiles[b] = t;
         for (int d = 0; d < ndim; ++d) {
             if (B.n[d] < 1) return fail(MHDPIC_EINVAL, "cell counts must be >= 1");
             if (!(B.dx[d] > 0.0) || !std::isfinite(B.dx[d])) return fail(MHDPIC_EINVAL, "dx must be > 0");
@@ -213,7 +220,7 @@ int validate_boxes(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
 }
 
 Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32_t precision,
-                   int ndim, const TileShape& tile) {
+                   int ndim, const std::vector<TileShape>& tiles) {
     Layout L;
     for (int b = 0; b < nb; ++b) {
         const mhdpic_box& B = boxes[b];
@@ -221,6 +228,7 @@ Layout make_layout(const mhdpic_box* boxes, int32_t nb, const int64_t* np, int32
         L.N0 += np[b];
         L.tagged = L.tagged || B.capacity > 0;
         L.NC += (int64_t)B.n[0] * B.n[1] * (ndim == 3 ? B.n[2] : 1);
+        const TileShape& tile = tiles[b];
         int ntx = (B.n[0] + tile.x - 1) / tile.x, nty = (B.n[1] + tile.y - 1) / tile.y;
         int ntz = ndim == 3 ? (B.n[2] + tile.z - 1) / tile.z : 1;
         L.NT += ntx * nty * ntz;
@@ -365,7 +373,6 @@ enum BinKeys {
 template <int NDIM, typename PS, typename T>
 int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
     const Layout& L = c->L;
-    const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
     PS A = part<PS, T>(c, c->cur);
     PS Bo = part<PS, T>(c, 1 - c->cur);
     const BoxDev* bd = at<BoxDev>(c, L.boxes);
@@ -374,7 +381,7 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
     if (keys == kKeysRekey)
         hipLaunchKernelGGL((k_rekey_items<Pol, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
                            at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
-                           at<uint32_t>(c, L.n_items[it]), bd, T3, at<uint32_t>(c, L.err));
+                           at<uint32_t>(c, L.n_items[it]), bd, at<uint32_t>(c, L.err));
     else if (keys == kKeysStay)
         hipLaunchKernelGGL((k_stay_items<PS, NDIM>), dim3(item_grid(L)), dim3(256), 0, s, A,
                            at<uint16_t>(c, L.code), at<uint32_t>(c, L.cnt), at<WorkItem>(c, L.items[it]),
@@ -430,7 +437,6 @@ PS shifted(PS P, int64_t off) {
 template <int NDIM, typename PS, typename T>
 int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n, int64_t slot0, bool tail) {
     const Layout& L = c->L;
-    const int3 T3 = make_int3(c->tile.x, c->tile.y, c->tile.z);
     const int src = tail ? 1 - c->cur : c->cur, dst = tail ? c->cur : 1 - c->cur;
     PS A = shifted(part<PS, T>(c, src), slot0);
     PS Bo = shifted(part<PS, T>(c, dst), slot0);
@@ -450,11 +456,11 @@ int launch_sort(mhdpic_ctx* c, hipStream_t s, int64_t n, int64_t slot0, bool tai
     if (n > 0 && lds)
         hipLaunchKernelGGL((k_key_count_lds<NDIM, PS>), dim3(gC), dim3(256), hbytes, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           sb, n, T3, L.NT);
+                           sb, n, L.NT);
     else if (n > 0)
         hipLaunchKernelGGL((k_key_cell<NDIM, PS>), dim3(grid_for(n, 256)), dim3(256), 0, s, A,
                            at<uint32_t>(c, L.key), at<uint32_t>(c, L.count), at<BoxDev>(c, L.boxes),
-                           sb, n, T3);
+                           sb, n);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, at<uint32_t>(c, L.count),
                        at<uint32_t>(c, tail ? L.tail_start : L.start), at<uint32_t>(c, L.cursor),
                        at<int32_t>(c, L.tile_box), at<WorkItem>(c, tail ? L.tail_items : L.items[0]),
@@ -485,10 +491,12 @@ int launch_sort_any(mhdpic_ctx* c, hipStream_t s, int64_t n, int64_t slot0, bool
 }
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
-int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
-    // two blocks of eight waves per CU (four per SIMD)
-    constexpr int BLOCK = PushShape<Pol, NDIM>::BLOCK;
+int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred, int grp) {
+    // four waves per SIMD: two blocks of eight waves per CU, or one of
+    // sixteen when the LDS boxes of the tile take more than half the CU's LDS
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
+    constexpr int BLOCK = G::lds_bytes() > kLdsPerCU / 2 ? 2 * PushShape<Pol, NDIM>::BLOCK
+                                                         : PushShape<Pol, NDIM>::BLOCK;
     using R = typename Pol::R;
     const Layout& L = c->L;
     PushArgsT<Pol> a;
@@ -504,17 +512,28 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred) {
     a.err = at<uint32_t>(c, L.err);
     a.NC = L.NC;
     a.do_pred = do_pred ? 1 : 0;
+    a.grp = c->grp_shape.size() > 1 ? grp : -1;
     size_t lds = G::lds_bytes();
     auto kern = k_push<Pol, NDIM, TX, TY, TZ, BLOCK>;
     if (lds > 65536) HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->grp_timing) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
     hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s, a);
+    if (c->grp_timing) {
+        HIP_TRY(hipEventRecord(e1, s));
+        c->grp_marks.push_back({grp, e0, e1});
+    }
     return MHDPIC_OK;
 }
 
 template <int NDIM, int TX, int TY, int TZ>
-int launch_push_t(mhdpic_ctx* c, hipStream_t s, bool p) {
-    if (c->precision == MHDPIC_FP64) return launch_push_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, p);
-    return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, p);
+int launch_push_t(mhdpic_ctx* c, hipStream_t s, bool p, int grp) {
+    if (c->precision == MHDPIC_FP64) return launch_push_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, p, grp);
+    return launch_push_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, p, grp);
 }
 
 // What a tiled n_CR, J_CR deposit covers: a work list and, for a removal by
@@ -527,7 +546,7 @@ struct DepositJob {
 };
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
-int launch_deposit_pol(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
+int launch_deposit_pol(mhdpic_ctx* c, hipStream_t s, const DepositJob& job, int grp) {
     constexpr int BLOCK = 256;
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
@@ -539,34 +558,41 @@ int launch_deposit_pol(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
     hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s,
                        part<typename Pol::Part, R>(c, c->cur),
                        at<int64_t>(c, c->nj == 0 ? L.nJ0 : L.nJ1), L.NC, at<BoxDev>(c, L.boxes),
-                       job.items, job.n_items, at<uint32_t>(c, L.err), job.t_cut, job.t_now);
+                       job.items, job.n_items, at<uint32_t>(c, L.err), job.t_cut, job.t_now,
+                       c->grp_shape.size() > 1 ? grp : -1);
     return MHDPIC_OK;
 }
 
 template <int NDIM, int TX, int TY, int TZ>
-int launch_deposit_t(mhdpic_ctx* c, hipStream_t s, const DepositJob& job) {
-    if (c->precision == MHDPIC_FP64) return launch_deposit_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, job);
-    return launch_deposit_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, job);
+int launch_deposit_t(mhdpic_ctx* c, hipStream_t s, const DepositJob& job, int grp) {
+    if (c->precision == MHDPIC_FP64) return launch_deposit_pol<F64Pol, NDIM, TX, TY, TZ>(c, s, job, grp);
+    return launch_deposit_pol<F32Pol, NDIM, TX, TY, TZ>(c, s, job, grp);
 }
 
-// Calls F<NDIM, TX, TY, TZ>(c, s, flag) for the context's (compiled) tile.
+// Calls F<NDIM, TX, TY, TZ>(c, s, flag, g) for each launch group g of the
+// context, with the group's (compiled) tile shape.
 #define MHDPIC_TILE_DISPATCH(F, c, s, flag)                                                  \
     do {                                                                                     \
-        const TileShape& t_ = (c)->tile;                                                     \
-        if ((c)->ndim == 2) {                                                                \
-            if (t_.x == 16 && t_.y == 16) return F<2, 16, 16, 1>(c, s, flag);               \
-            if (t_.x == 32 && t_.y == 16) return F<2, 32, 16, 1>(c, s, flag);               \
-            if (t_.x == 8 && t_.y == 8) return F<2, 8, 8, 1>(c, s, flag);                   \
-            if (t_.x == 32 && t_.y == 32) return F<2, 32, 32, 1>(c, s, flag);               \
-            if (t_.x == 64 && t_.y == 16) return F<2, 64, 16, 1>(c, s, flag);               \
-        } else {                                                                             \
-            if (t_.x == 8 && t_.y == 4 && t_.z == 4) return F<3, 8, 4, 4>(c, s, flag);      \
-            if (t_.x == 8 && t_.y == 8 && t_.z == 4) return F<3, 8, 8, 4>(c, s, flag);      \
-            if (t_.x == 4 && t_.y == 4 && t_.z == 4) return F<3, 4, 4, 4>(c, s, flag);      \
-            if (t_.x == 8 && t_.y == 8 && t_.z == 8) return F<3, 8, 8, 8>(c, s, flag);      \
-            if (t_.x == 16 && t_.y == 4 && t_.z == 4) return F<3, 16, 4, 4>(c, s, flag);    \
+        for (int g_ = 0; g_ < (int)(c)->grp_shape.size(); ++g_) {                            \
+            const TileShape& t_ = (c)->grp_shape[g_];                                        \
+            int rc_ = 1; /* no compiled kernel */                                            \
+            if ((c)->ndim == 2) {                                                            \
+                if (t_.x == 16 && t_.y == 16) rc_ = F<2, 16, 16, 1>(c, s, flag, g_);        \
+                else if (t_.x == 32 && t_.y == 16) rc_ = F<2, 32, 16, 1>(c, s, flag, g_);   \
+                else if (t_.x == 8 && t_.y == 8) rc_ = F<2, 8, 8, 1>(c, s, flag, g_);       \
+                else if (t_.x == 32 && t_.y == 32) rc_ = F<2, 32, 32, 1>(c, s, flag, g_);   \
+                else if (t_.x == 64 && t_.y == 16) rc_ = F<2, 64, 16, 1>(c, s, flag, g_);   \
+            } else {                                                                         \
+                if (t_.x == 8 && t_.y == 4 && t_.z == 4) rc_ = F<3, 8, 4, 4>(c, s, flag, g_);        \
+                else if (t_.x == 8 && t_.y == 8 && t_.z == 4) rc_ = F<3, 8, 8, 4>(c, s, flag, g_);   \
+                else if (t_.x == 4 && t_.y == 4 && t_.z == 4) rc_ = F<3, 4, 4, 4>(c, s, flag, g_);   \
+                else if (t_.x == 8 && t_.y == 8 && t_.z == 8) rc_ = F<3, 8, 8, 8>(c, s, flag, g_);   \
+                else if (t_.x == 16 && t_.y == 4 && t_.z == 4) rc_ = F<3, 16, 4, 4>(c, s, flag, g_); \
+            }                                                                                \
+            if (rc_ == 1) return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");  \
+            if (rc_) return rc_;                                                             \
         }                                                                                    \
-        return fail(MHDPIC_ENOTSUP, "tile shape has no compiled kernel");                   \
+        return MHDPIC_OK;                                                                    \
     } while (0)
 
 // Adds n_CR, J_CR of the particles of a work list (the current one unless
@@ -784,8 +810,8 @@ namespace {
 // The device record of box B.  cell_off, part_off and tile_off are the cells,
 // particles and tiles of the boxes before it; the step constants stay zero
 // until a step sets them.
-BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int64_t cell_off,
-                   int64_t part_off, int64_t np, int32_t tile_off) {
+BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int32_t grp,
+                   int64_t cell_off, int64_t part_off, int64_t np, int32_t tile_off) {
     BoxDev d{};
     for (int k = 0; k < 3; ++k) {
         d.n[k] = (k < ndim) ? B.n[k] : 1;
@@ -801,6 +827,8 @@ BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int64_t
     const LdsStrides st = lds_strides(tile.x, tile.y, ndim == 3 ? tile.z : 1, ndim);
     d.lds_sx = st.sx;
     d.lds_sp = st.sp;
+    for (int k = 0; k < 3; ++k) d.T[k] = T[k];
+    d.grp = grp;
     for (int k = 0; k < 3; ++k) {
         d.face[k][0] = B.boundary[k][0];
         d.face[k][1] = B.boundary[k][1];
@@ -821,14 +849,17 @@ BoxDev make_boxdev(const mhdpic_box& B, int ndim, const TileShape& tile, int64_t
 }
 
 // Host fields of a context over the caller's workspace; nothing is enqueued.
+// Boxes of one tile shape form one launch group; with size_class (the
+// autotuner), boxes of one shape and one class do.
 int open_context(mhdpic_ctx* c, const mhdpic_box* boxes, int32_t n_boxes, const int64_t* np,
                  int32_t precision, void* workspace, size_t ws_bytes, const double* x,
-                 const double* v, const double* m, const double* qm) {
+                 const double* v, const double* m, const double* qm,
+                 const int32_t* size_class = nullptr) {
     int ndim;
-    TileShape tile;
-    int rc = validate_boxes(boxes, n_boxes, np, precision, ndim, tile);
+    std::vector<TileShape> tiles;
+    int rc = validate_boxes(boxes, n_boxes, np, precision, ndim, tiles);
     if (rc) return rc;
-    Layout L = make_layout(boxes, n_boxes, np, precision, ndim, tile);
+    Layout L = make_layout(boxes, n_boxes, np, precision, ndim, tiles);
     if (!workspace) return fail(MHDPIC_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace) % kAlign) return fail(MHDPIC_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total) return fail(MHDPIC_ENOMEM, "workspace too small");
@@ -836,7 +867,23 @@ int open_context(mhdpic_ctx* c, const mhdpic_box* boxes, int32_t n_boxes, const 
     c->ndim = ndim;
     c->precision = precision;
     c->nb = n_boxes;
-    c->tile = tile;
+    c->box_tile = tiles;
+    c->box_grp.assign(n_boxes, 0);
+    c->grp_shape.clear();
+    std::vector<int32_t> grp_class;
+    for (int b = 0; b < n_boxes; ++b) {
+        const int32_t cls = size_class ? size_class[b] : 0;
+        int g = 0;
+        while (g < (int)c->grp_shape.size() &&
+               !(c->grp_shape[g].x == tiles[b].x && c->grp_shape[g].y == tiles[b].y &&
+                 c->grp_shape[g].z == tiles[b].z && grp_class[g] == cls))
+            ++g;
+        if (g == (int)c->grp_shape.size()) {
+            c->grp_shape.push_back(tiles[b]);
+            grp_class.push_back(cls);
+        }
+        c->box_grp[b] = g;
+    }
     c->L = L;
     c->ws = static_cast<unsigned char*>(workspace);
     return MHDPIC_OK;
@@ -907,7 +954,8 @@ int init_device(mhdpic_ctx* c, const mhdpic_box* boxes, const int64_t* np, const
         const int nc = std::min(kChunk, nb - b0);
         for (int k = 0; k < nc; ++k) {
             const mhdpic_box& B = boxes[b0 + k];
-            BoxDev d = make_boxdev(B, c->ndim, c->tile, cell_off, part_off, np[b0 + k], tile_off);
+            BoxDev d = make_boxdev(B, c->ndim, c->box_tile[b0 + k], c->box_grp[b0 + k], cell_off,
+                                   part_off, np[b0 + k], tile_off);
             if (dt) set_step(d, B, c->ndim, dt[b0 + k], n_sub);
             cell_off += (int64_t)d.n[0] * d.n[1] * d.n[2];
             part_off += np[b0 + k];
@@ -1058,6 +1106,13 @@ namespace {
 
 }  // namespace
 
+namespace {
+int init_ctx(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+             int32_t precision, const double* x, const double* v, const double* m,
+             const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
+             mhdpic_ctx** out, const int32_t* size_class);
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1070,10 +1125,10 @@ int mhdpic_workspace_size(const mhdpic_box* boxes, int32_t n_boxes, const int64_
                           int32_t precision, size_t* bytes) {
     if (!bytes) return fail(MHDPIC_EINVAL, "bytes is NULL");
     int ndim;
-    TileShape tile;
-    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
+    std::vector<TileShape> tiles;
+    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tiles);
     if (rc) return rc;
-    *bytes = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile).total;
+    *bytes = make_layout(boxes, n_boxes, n_particles, precision, ndim, tiles).total;
     return MHDPIC_OK;
 }
 
@@ -1081,10 +1136,23 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
                 int32_t precision, const double* x, const double* v, const double* m,
                 const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
                 mhdpic_ctx** out) {
+    return init_ctx(boxes, n_boxes, n_particles, precision, x, v, m, qm, workspace, ws_bytes,
+                    hip_stream, out, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+int init_ctx(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+             int32_t precision, const double* x, const double* v, const double* m,
+             const double* qm, void* workspace, size_t ws_bytes, void* hip_stream,
+             mhdpic_ctx** out, const int32_t* size_class) {
     if (!out) return fail(MHDPIC_EINVAL, "out is NULL");
     *out = nullptr;
     mhdpic_ctx* c = new mhdpic_ctx();
-    int rc = open_context(c, boxes, n_boxes, n_particles, precision, workspace, ws_bytes, x, v, m, qm);
+    int rc = open_context(c, boxes, n_boxes, n_particles, precision, workspace, ws_bytes, x, v, m, qm,
+                          size_class);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     c->last_stream = s;
     if (!rc && hipHostMalloc((void**)&c->err_host, 4, hipHostMallocDefault) != hipSuccess)
@@ -1109,16 +1177,20 @@ int mhdpic_init(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_parti
     return MHDPIC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int mhdpic_advance_noalloc(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
                            int32_t precision, const double* x, const double* v, const double* m,
                            const double* qm, const double* B, const double* vg, const double* rho,
                            const double* dt, int32_t n_steps, int32_t n_sub, double* x_out,
                            double* v_out, int64_t* deposits_out, void* hip_stream) {
     int ndim;
-    TileShape tile;
-    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tile);
+    std::vector<TileShape> tiles;
+    int rc = validate_boxes(boxes, n_boxes, n_particles, precision, ndim, tiles);
     if (rc) return rc;
-    const size_t need = make_layout(boxes, n_boxes, n_particles, precision, ndim, tile).total;
+    const size_t need = make_layout(boxes, n_boxes, n_particles, precision, ndim, tiles).total;
     if (need > kScratchBytes) {
         std::snprintf(g_last_error, sizeof(g_last_error),
                       "mhdpic_advance_noalloc: these boxes and particles need %zu bytes of scratch; "
@@ -1278,6 +1350,164 @@ int mhdpic_autotune(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_p
     tile_out[1] = best.y;
     tile_out[2] = best.z;
     if (ms_per_step) *ms_per_step = best_ms / n_steps;
+    return MHDPIC_OK;
+}
+
+int mhdpic_autotune_classes_workspace_size(const mhdpic_box* boxes, int32_t n_boxes,
+                                           const int64_t* n_particles, int32_t precision,
+                                           size_t* bytes) {
+    if (!bytes || !boxes || n_boxes < 1) return fail(MHDPIC_EINVAL, "NULL argument");
+    size_t best = 0;
+    int rc = mhdpic_autotune_workspace_size(boxes, n_boxes, n_particles, precision, &best);
+    if (rc) return rc;
+    // the mix with the most tiles: each box with its candidate of most tiles
+    const int ndim = boxes[0].ndim;
+    std::vector<mhdpic_box> b(boxes, boxes + n_boxes);
+    for (mhdpic_box& B : b) {
+        int most = -1;
+        for (const TileShape& t : tile_candidates(ndim, precision)) {
+            const int nt = ((B.n[0] + t.x - 1) / t.x) * ((B.n[1] + t.y - 1) / t.y) *
+                           (ndim == 3 ? (B.n[2] + t.z - 1) / t.z : 1);
+            if (nt > most) {
+                most = nt;
+                B.tile[0] = t.x;
+                B.tile[1] = t.y;
+                B.tile[2] = ndim == 3 ? t.z : 1;
+            }
+        }
+    }
+    size_t sz = 0;
+    rc = mhdpic_workspace_size(b.data(), n_boxes, n_particles, precision, &sz);
+    if (rc) return rc;
+    *bytes = std::max(best, sz);
+    return MHDPIC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Size class of a box for the autotuner: cells in [4^k, 4^(k+1)).
+int32_t size_class_of(const mhdpic_box& B) {
+    int64_t cells = (int64_t)B.n[0] * B.n[1] * (B.ndim == 3 ? B.n[2] : 1);
+    int32_t k = 0;
+    while (cells >= 4) {
+        cells /= 4;
+        ++k;
+    }
+    return k;
+}
+
+// Times n_steps steps of a context built from boxes b (events on stream s);
+// with size classes, also the push time of each launch group (ms, summed).
+int time_steps(const std::vector<mhdpic_box>& b, const int64_t* np, int32_t precision,
+               const double* x, const double* v, const double* m, const double* qm,
+               const double* B, const double* vg, const double* rho, const double* dt,
+               int32_t n_steps, void* ws, size_t ws_bytes, void* stream, const int32_t* cls,
+               float* ms_out, std::vector<float>* grp_ms, std::vector<TileShape>* grp_shape,
+               std::vector<int32_t>* box_grp) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mhdpic_ctx* c = nullptr;
+    int rc = init_ctx(b.data(), (int32_t)b.size(), np, precision, x, v, m, qm, ws, ws_bytes, stream,
+                      &c, cls);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = mhdpic_step(c, B, vg, rho, dt, 2, stream);  // warm-up, uploads dt
+    if (!rc && hipEventCreate(&e0) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventCreate");
+    if (!rc && hipEventCreate(&e1) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventCreate");
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipStreamSynchronize");
+    c->grp_timing = grp_ms != nullptr;
+    if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventRecord");
+    if (!rc) rc = mhdpic_step(c, B, vg, rho, dt, n_steps, stream);
+    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventRecord");
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventSynchronize");
+    if (!rc && hipEventElapsedTime(ms_out, e0, e1) != hipSuccess) rc = fail(MHDPIC_EDEVICE, "hipEventElapsedTime");
+    if (!rc && grp_ms) {
+        grp_ms->assign(c->grp_shape.size(), 0.0f);
+        for (auto& mk : c->grp_marks) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, mk.a, mk.b) == hipSuccess) (*grp_ms)[mk.grp] += t;
+        }
+        if (grp_shape) *grp_shape = c->grp_shape;
+        if (box_grp) *box_grp = c->box_grp;
+    }
+    if (!rc) rc = mhdpic_check(c, stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    mhdpic_destroy(c);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhdpic_autotune_classes(const mhdpic_box* boxes, int32_t n_boxes, const int64_t* n_particles,
+                            int32_t precision, const double* x, const double* v, const double* m,
+                            const double* qm, const double* B, const double* vg, const double* rho,
+                            const double* dt, int32_t n_steps, void* workspace, size_t ws_bytes,
+                            void* hip_stream, int32_t* tiles_out, double* ms_per_step) {
+    if (!boxes || n_boxes < 1 || !tiles_out || n_steps < 1)
+        return fail(MHDPIC_EINVAL, "NULL argument or n_steps < 1");
+    const int ndim = boxes[0].ndim;
+    std::vector<int32_t> cls(n_boxes);
+    int32_t ncls = 0;
+    for (int b = 0; b < n_boxes; ++b) {
+        cls[b] = size_class_of(boxes[b]);
+        ncls = std::max(ncls, cls[b] + 1);
+    }
+    // push time of each size class under each candidate shape, and the whole
+    // step with one shape for all boxes
+    std::vector<float> best_cls_ms(ncls, 0.0f);
+    std::vector<TileShape> best_cls(ncls, TileShape{0, 0, 0});
+    float best_all_ms = 0.0f;
+    TileShape best_all{0, 0, 0};
+    for (const TileShape& t : tile_candidates(ndim, precision)) {
+        std::vector<mhdpic_box> b = with_tile(boxes, n_boxes, t);
+        float ms = 0.0f;
+        std::vector<float> gms;
+        std::vector<TileShape> gshape;
+        std::vector<int32_t> bgrp;
+        int rc = time_steps(b, n_particles, precision, x, v, m, qm, B, vg, rho, dt, n_steps, workspace,
+                            ws_bytes, hip_stream, cls.data(), &ms, &gms, &gshape, &bgrp);
+        if (rc) return rc;
+        if (best_all.x == 0 || ms < best_all_ms) {
+            best_all_ms = ms;
+            best_all = t;
+        }
+        std::vector<float> per_cls(ncls, 0.0f);
+        std::vector<bool> seen(ncls, false);
+        for (int bx = 0; bx < n_boxes; ++bx) {
+            if (seen[cls[bx]]) continue;
+            seen[cls[bx]] = true;
+            per_cls[cls[bx]] = gms[bgrp[bx]];
+        }
+        for (int k = 0; k < ncls; ++k)
+            if (seen[k] && (best_cls[k].x == 0 || per_cls[k] < best_cls_ms[k])) {
+                best_cls_ms[k] = per_cls[k];
+                best_cls[k] = t;
+            }
+    }
+    // the per-class choice, kept only if its whole step beats the best single shape
+    std::vector<mhdpic_box> mix(boxes, boxes + n_boxes);
+    for (int b = 0; b < n_boxes; ++b) {
+        const TileShape& t = best_cls[cls[b]];
+        mix[b].tile[0] = t.x;
+        mix[b].tile[1] = t.y;
+        mix[b].tile[2] = ndim == 3 ? t.z : 1;
+    }
+    float mix_ms = 0.0f;
+    int rc = time_steps(mix, n_particles, precision, x, v, m, qm, B, vg, rho, dt, n_steps, workspace,
+                        ws_bytes, hip_stream, nullptr, &mix_ms, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    const bool use_mix = mix_ms < best_all_ms;
+    for (int b = 0; b < n_boxes; ++b) {
+        const TileShape& t = use_mix ? best_cls[cls[b]] : best_all;
+        tiles_out[3 * b + 0] = t.x;
+        tiles_out[3 * b + 1] = t.y;
+        tiles_out[3 * b + 2] = ndim == 3 ? t.z : 1;
+    }
+    if (ms_per_step) *ms_per_step = (use_mix ? mix_ms : best_all_ms) / n_steps;
     return MHDPIC_OK;
 }
 
@@ -1505,6 +1735,11 @@ int mhdpic_destroy(mhdpic_ctx* c) {
         c->pool.push_back(mk.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    for (auto& mk : c->grp_marks) {
+        (void)hipEventSynchronize(mk.b);
+        (void)hipEventDestroy(mk.a);
+        (void)hipEventDestroy(mk.b);
+    }
     if (c->err_event) {
         (void)hipEventSynchronize(c->err_event);
         (void)hipEventDestroy(c->err_event);

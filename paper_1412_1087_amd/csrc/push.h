@@ -34,6 +34,7 @@ struct PushArgsT {
     uint32_t* err;
     int64_t NC;
     int32_t do_pred;             // 0: skip n_CR, J_CR (a sub-step before the last)
+    int32_t grp;                 // launch group of this launch's boxes, -1: all boxes
 };
 
 template <class Pol, int NDIM, int TX, int TY, int TZ>
@@ -236,6 +237,7 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     for (int c = threadIdx.x; c < K; c += BLOCK) s_cnt[c] = 0;
     const WorkItem w = a.items[item];
     const BoxDev bx = a.boxes[w.box];  // a copy: kept in registers across the stores
+    if (a.grp >= 0 && bx.grp != a.grp) return;  // a box of another tile shape
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);
@@ -485,7 +487,8 @@ template <class Pol, int NDIM, int TX, int TY, int TZ, int BLOCK, bool REMOVE>
 __global__ void __launch_bounds__(BLOCK)
 k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
                    const BoxDev* __restrict__ boxes, const WorkItem* __restrict__ items,
-                   const uint32_t* __restrict__ n_items, uint32_t* err, double t_cut, double t_now) {
+                   const uint32_t* __restrict__ n_items, uint32_t* err, double t_cut, double t_now,
+                   int grp) {
     using G = Geo<Pol, NDIM, TX, TY, TZ>;
     using R = typename Pol::R;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -495,6 +498,7 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
     if (!item_of_block(n_items, item)) return;
     const WorkItem w = items[item];
     const BoxDev& bx = boxes[w.box];
+    if (grp >= 0 && bx.grp != grp) return;  // a box of another tile shape
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);

@@ -28,6 +28,7 @@ EXPORTED = [
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
     "mhdpic_feedback", "mhdpic_step_graph_sub", "mhdpic_advance", "mhdpic_advance_noalloc",
     "mhdpic_particles_read_ids", "mhdpic_counts", "mhdpic_inject", "mhdpic_remove_tagged",
+    "mhdpic_autotune_classes_workspace_size", "mhdpic_autotune_classes",
 ]
 
 
@@ -105,6 +106,16 @@ def lib():
                                       ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
                                       ct.POINTER(ct.c_double), ct.c_int32, vp, sz, vp,
                                       ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
+        L.mhdpic_autotune_classes_workspace_size.restype = ct.c_int
+        L.mhdpic_autotune_classes_workspace_size.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32,
+                                                             ct.POINTER(ct.c_int64), ct.c_int32,
+                                                             ct.POINTER(sz)]
+        L.mhdpic_autotune_classes.restype = ct.c_int
+        L.mhdpic_autotune_classes.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32,
+                                              ct.POINTER(ct.c_int64), ct.c_int32, vp, vp, vp, vp,
+                                              vp, vp, vp, ct.POINTER(ct.c_double), ct.c_int32, vp,
+                                              sz, vp, ct.POINTER(ct.c_int32),
+                                              ct.POINTER(ct.c_double)]
         L.mhdpic_advance.restype = ct.c_int
         L.mhdpic_advance.argtypes = [ct.POINTER(MhdpicBox), ct.c_int32, ct.POINTER(ct.c_int64),
                                      ct.c_int32, vp, vp, vp, vp, vp, vp, vp,
@@ -356,6 +367,30 @@ def autotune(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, v
                                  _ptr(ws), int(size.value), _stream(stream), tile, ct.byref(ms)))
     del ws
     return (int(tile[0]), int(tile[1]), int(tile[2])), float(ms.value)
+
+
+def autotune_classes(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg, rho,
+                     dt, n_steps: int = 10, precision: int = FP64, stream=None):
+    """Tile shape per box (per box-size class) and the chosen step time in ms
+    (library autotuner of the batched form)."""
+    arr = _boxes_array(boxes)
+    nb = len(boxes)
+    npart = (ct.c_int64 * nb)(*[int(a) for a in n_particles])
+    size = ct.c_size_t()
+    _check(lib().mhdpic_autotune_classes_workspace_size(arr, nb, npart, int(precision),
+                                                        ct.byref(size)))
+    ws = torch.empty(max(int(size.value), 256), dtype=torch.uint8, device=x.device)
+    if isinstance(dt, (int, float)):
+        dt = [float(dt)] * nb
+    dts = (ct.c_double * nb)(*[float(a) for a in dt])
+    tiles = (ct.c_int32 * (3 * nb))()
+    ms = ct.c_double()
+    _check(lib().mhdpic_autotune_classes(arr, nb, npart, int(precision), _ptr(x), _ptr(v), _ptr(m),
+                                         _ptr(qm), _ptr(B), _ptr(vg), _ptr(rho), dts, int(n_steps),
+                                         _ptr(ws), int(size.value), _stream(stream), tiles,
+                                         ct.byref(ms)))
+    del ws
+    return [tuple(int(tiles[3 * b + k]) for k in range(3)) for b in range(nb)], float(ms.value)
 
 
 def advance(boxes: Sequence[Box], n_particles: Sequence[int], x, v, m, qm, B, vg, rho, dt,

@@ -39,7 +39,9 @@ class DeviceRun:
         if not isinstance(wls, (list, tuple)):
             wls = [wls]
         self.wls = list(wls)
-        self.boxes = [gpu_box(w.box, tile) for w in self.wls]
+        # tile: one shape for every box, or a list with one shape per box
+        tiles = tile if (len(tile) and isinstance(tile[0], (tuple, list))) else [tile] * len(self.wls)
+        self.boxes = [gpu_box(w.box, t) for w, t in zip(self.wls, tiles)]
         x = np.concatenate([w.x for w in self.wls], axis=1)
         v = np.concatenate([w.v for w in self.wls], axis=1)
         m = np.concatenate([w.m for w in self.wls])

@@ -100,6 +100,65 @@ def test_autotune_picks_a_compiled_shape_that_stays_exact():
     assert (D == o.D).all()
 
 
+def test_boxes_with_different_tile_shapes_match_oracle_eager_and_graph():
+    """One context whose boxes use three tile shapes (one push launch per
+    shape), eager and graph-captured, bit-exact against the oracle."""
+    _need_gpu()
+    wls = _boxes(n=9, seed0=990)
+    shapes = [(16, 16, 1), (32, 16, 1), (8, 8, 1)]
+    tiles = [shapes[b % 3] for b in range(len(wls))]
+    eager = DeviceRun(wls, tile=tiles)
+    graph = DeviceRun(wls, tile=tiles)
+    oracles = [oracle_run(w) for w in wls]
+    stream = torch.cuda.Stream()
+    dts = [w.dt for w in wls]
+    for rep in range(2):
+        eager.step(2, dts=dts)
+        with torch.cuda.stream(stream):
+            graph.ctx.step_graph(graph.B, graph.vg, graph.rho, dts, 2, stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for w, o in zip(wls, oracles):
+            o.step(w.B, w.vg, w.rho, w.dt, 2)
+        De, Dg = eager.deposits(), graph.deposits()
+        pe, pg = eager.particles(), graph.particles()
+        for b, o in enumerate(oracles):
+            assert (De[b] == o.D).all(), f"replay {rep}: box {b} eager != oracle"
+            assert (Dg[b] == o.D).all(), f"replay {rep}: box {b} graph != oracle"
+            assert_states_exact(pe[b][0], pe[b][1], o.positions(), o.v, f"box {b}")
+            assert (pg[b][1] == pe[b][1]).all()
+    eager.ctx.check()
+    graph.ctx.check()
+
+
+def test_class_autotuner_gives_compiled_shapes_per_box_that_stay_exact():
+    _need_gpu()
+    from paper_1412_1087_amd import mhdpic as M
+    from gpu_helpers import gpu_box, to_dev
+    wls = W.batch2d(n_boxes=12, seed0=1990, side=(16, 96), ppc=(2, 6))
+    cat = lambda f: np.concatenate([f(w) for w in wls], axis=-1)
+    tiles, ms = M.autotune_classes([gpu_box(w.box) for w in wls], [w.N for w in wls],
+                                   to_dev(cat(lambda w: w.x)), to_dev(cat(lambda w: w.v)),
+                                   to_dev(cat(lambda w: w.m)), to_dev(cat(lambda w: w.qm)),
+                                   to_dev(cat(lambda w: w.B)), to_dev(cat(lambda w: w.vg)),
+                                   to_dev(cat(lambda w: w.rho)), [w.dt for w in wls], n_steps=4)
+    assert len(tiles) == len(wls) and ms > 0
+    compiled = [(16, 16, 1), (32, 16, 1), (8, 8, 1), (32, 32, 1), (64, 16, 1)]
+    assert all(t in compiled for t in tiles)
+    # boxes of one size class share a shape
+    cls = [int(np.log2(w.box.n_cells) // 2) for w in wls]
+    for k in set(cls):
+        assert len({t for t, c in zip(tiles, cls) if c == k}) == 1
+    g = DeviceRun(wls, tile=tiles)
+    oracles = [oracle_run(w) for w in wls]
+    g.step(2)
+    for w, o in zip(wls, oracles):
+        o.step(w.B, w.vg, w.rho, w.dt, 2)
+    D = g.deposits()
+    for b, o in enumerate(oracles):
+        assert (D[b] == o.D).all(), b
+
+
 def test_graph_subcycled_replays_match_eager_and_oracle():
     _need_gpu()
     wls = _boxes(n=4, seed0=980)
