@@ -18,14 +18,15 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("eps,lam,t_end", [(0.1, 0.0, 0.6), (0.01, 2.0, 0.3)])
-def test_bell_growth_on_the_gpu_follows_the_oracle(eps, lam, t_end):
+@pytest.mark.parametrize("eps,lam", [(0.1, 0.0), (0.01, 20.0)])
+def test_bell_growth_on_the_gpu_follows_the_oracle(eps, lam):
     _need_gpu()
-    st = BellSetup(eps=eps, hall_lambda=lam)
-    ts, a_gpu = run(st, GpuBackend(st), t_end=t_end, dt=st.dt_max)
-    _, a_ora = run(st, OracleBackend(st), t_end=t_end, dt=st.dt_max)
+    st = BellSetup(eps=eps, hall_lambda=lam, nx=64)
+    g0, _ = dispersion(st)
+    ts, a_gpu = run(st, GpuBackend(st), t_end=4.5 / g0, dt=st.dt_max)
+    _, a_ora = run(st, OracleBackend(st), t_end=4.5 / g0, dt=st.dt_max)
     assert np.array_equal(a_gpu, a_ora)
-    growth, omega_r = measured_rates(ts, a_gpu, t0=0.05)
+    growth, omega_r = measured_rates(ts, a_gpu, t0=2.0 / g0)
     g_exact, vph_exact = dispersion(st)
-    assert abs(growth / g_exact - 1.0) < 0.02, (growth, g_exact)
-    assert abs(omega_r / st.km / vph_exact - 1.0) < 0.02, (omega_r / st.km, vph_exact)
+    assert abs(growth / g_exact - 1.0) < 0.005, (growth, g_exact)
+    assert abs(omega_r / st.km / vph_exact - 1.0) < 0.005, (omega_r / st.km, vph_exact)
