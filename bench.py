@@ -618,6 +618,16 @@ def main():
                           "data": "synthetic (seeded; the shock set-up of Sec. 5)",
                           "config": {"workload": out["workload"]}, "shock_wall": out}), flush=True)
         return
+    if args.workload == "precision":
+        # the precision form alone (profiling runs): binary32 and binary64 on
+        # the 128^3 box, the one-step error, and the feedback kernel
+        out = run_precision_form(args.steps, args.warmup)
+        print(json.dumps({"metric": "particle-updates/s (gather+push+deposit)", "value": out["value"],
+                          "unit": "particle-updates/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+                          "data": DATA_NOTE["bell3d128"],
+                          "config": {"workload": out["workload"]}, "fp32_mixed": out}), flush=True)
+        return
     if args.workload == "batch2d":
         # the batched form alone (profiling runs): steps as one graph launch
         out = run_batched_form(args.steps)
@@ -641,7 +651,7 @@ def main():
     alg = algorithmic_bytes(wl.box.ndim, N, g["n_cells"], fsz=fsz, msz=fsz)
     push_avg_s = push_ms * 1e-3 / max(push_n, 1)
     achieved = alg["per_launch"] / push_avg_s / 1e9
-    traffic = load_traffic(label, alg["per_launch"])
+    traffic = load_traffic(label + ("/fp32" if prec else ""), alg["per_launch"])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel="k_push_f32" if prec else "k_push_f64",
