@@ -59,10 +59,14 @@ struct Geo {
     }
     // padding cells come out beyond the box (lx >= TX + 2 or ly >= TY + 2)
     __device__ static __forceinline__ void coords(int p, int& lx, int& ly, int& lz) {
-        const int r = NDIM == 3 ? p % SP : p;
+        int r = p;
+        lz = 0;
+        if constexpr (NDIM == 3) {
+            r = p % SP;
+            lz = p / SP - 2;
+        }
         lx = r % SX - 2;
         ly = r / SX - 2;
-        lz = NDIM == 3 ? p / SP - 2 : 0;
     }
 };
 
