@@ -478,6 +478,18 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     }
 }
 
+// Tile-local index l (cell minus tile origin) of a tile of extent s in a box
+// of n cells, within one cell of the tile ([-1, s]), taking a periodic wrap
+// into account; kFar if it is farther.
+constexpr int kFar = -1000000;
+__device__ __forceinline__ int near_tile(int l, int s, int n, bool periodic) {
+    if (periodic) {
+        if (l < -1) l += n;
+        else if (l > s) l -= n;
+    }
+    return (l >= -1 && l <= s) ? l : kFar;
+}
+
 // n_CR = (q/mc) m and J_CR = (q/mc) m u at the current positions (App. A.1),
 // added to nJ for the particles of a work list (all particles at
 // initialisation, the new ones after an injection): the same LDS box and
@@ -519,17 +531,21 @@ k_deposit_nJ_tiled(typename Pol::Part P, int64_t* __restrict__ nJ, int64_t NC,
         if (REMOVE) {
             const double t = P.tag[j];
             if (!(t < t_cut && 2.0 * t <= t_now)) continue;
-            P.cell[j] = kDeadCell;
         }
         int i[3];
         unpack_cell<NDIM>(cell, i[0], i[1], i[2]);
-        int lx = i[0] - ox, ly = i[1] - oy, lz = NDIM == 3 ? i[2] - oz : 0;
-        if (!(lx >= 0 && lx < sx && ly >= 0 && ly < sy && lz >= 0 && lz < sz)) {
+        // the particle's cell relative to the tile: inside it after a sort by
+        // the current cell, or (after a step: the work list groups by the
+        // last half-step cell) up to one cell beyond it, across a periodic
+        // wrap of the box, as the push's own x^(n+1) deposit allows
+        const int lx = near_tile(i[0] - ox, sx, bx.n[0], bx.face[0][0] == FACE_PERIODIC);
+        const int ly = near_tile(i[1] - oy, sy, bx.n[1], bx.face[1][0] == FACE_PERIODIC);
+        const int lz = NDIM == 3 ? near_tile(i[2] - oz, sz, bx.n[2], bx.face[2][0] == FACE_PERIODIC) : 0;
+        if (lx == kFar || ly == kFar || lz == kFar) {
             errbits |= ERRBIT_STATE;
-            lx = min(max(lx, 0), sx - 1);
-            ly = min(max(ly, 0), sy - 1);
-            lz = NDIM == 3 ? min(max(lz, 0), sz - 1) : 0;
+            continue;
         }
+        if (REMOVE) P.cell[j] = kDeadCell;
         const int corner = G::index(lx, ly, lz) - G::CORNER;
         R wx[3], wy[3], wz[3] = {R(0), R(1), R(0)};
         Pol::weights(P.d[0][j], wx);

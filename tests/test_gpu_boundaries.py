@@ -173,6 +173,93 @@ def test_stacked_injections_removal_and_compaction_match_oracle():
     p.check("two graph steps after injection")
 
 
+def test_injection_into_boxes_of_different_tile_shapes():
+    """Two shock boxes of one context with different tile shapes (two push
+    launches per step): injections into both, removal, steps; each box
+    against its own oracle run."""
+    _need_gpu()
+    from paper_1412_1087_amd import mhdpic as M
+    sts = [W.shock_wall2d(nx=64, ny=8, front_cell=24), W.shock_wall2d(nx=48, ny=12, front_cell=20)]
+    tiles = [(16, 16, 1), (8, 8, 1)]
+    caps = [6000, 6000]
+    boxes = [gpu_box(st.box, t, st.boundary, c) for st, t, c in zip(sts, tiles, caps)]
+    z3, z1 = np.zeros((3, 0)), np.zeros(0)
+    ctx = M.Context(boxes, [0, 0], to_dev(z3), to_dev(z3), to_dev(z1), to_dev(z1))
+    ors = [O.System(oracle_box(st.box, st.boundary), z3, z3, z1, z1) for st in sts]
+    cat = lambda a, b: np.concatenate([a, b], axis=-1)
+    B = to_dev(cat(sts[0].B, sts[1].B))
+    vg = to_dev(cat(sts[0].vg, sts[1].vg))
+    rho = to_dev(cat(sts[0].rho, sts[1].rho))
+    tags = [np.zeros(0), np.zeros(0)]
+    gid = [[], []]  # library id of each oracle particle, per box
+    next_id = 0
+    t = 0.0
+    for k in range(6):
+        batch = [W.shock_injection(st, 300 + 50 * b, t, seed=1700 + 10 * k + b) for b, st in enumerate(sts)]
+        n0 = batch[0][0].shape[1]
+        gid[0] += list(range(next_id, next_id + n0))
+        gid[1] += list(range(next_id + n0, next_id + n0 + batch[1][0].shape[1]))
+        next_id += n0 + batch[1][0].shape[1]
+        ctx.inject([bt[0].shape[1] for bt in batch], *(to_dev(cat(batch[0][q], batch[1][q])) for q in range(5)))
+        for o, bt in zip(ors, batch):
+            o.inject(*bt[:4])
+        tags = [np.concatenate([tg, bt[4]]) for tg, bt in zip(tags, batch)]
+        ctx.step(B, vg, rho, [st.dt for st in sts], 1)
+        for o, st in zip(ors, sts):
+            o.step(st.B, st.vg, st.rho, st.dt, 1)
+        t += sts[0].dt
+        if k == 3:
+            ctx.remove_tagged(2.5 * sts[0].dt, t)
+            for o, tg in zip(ors, tags):
+                o.remove(np.flatnonzero((o.alive == 1) & (tg < 2.5 * sts[0].dt) & (2.0 * tg <= t)))
+    torch.cuda.synchronize()
+    D = ctx.deposit_read().cpu().numpy()
+    off = 0
+    for b, o in enumerate(ors):
+        nc = sts[b].box.n_cells
+        assert (D[:, off:off + nc] == o.D).all(), f"box {b} deposits"
+        off += nc
+    assert ctx.counts() == [int((o.alive == 1).sum()) for o in ors]
+    x, v, ids, tg = (a.cpu().numpy() for a in ctx.particles_read_ids())
+    col = {int(i): c for c, i in enumerate(ids)}
+    # ids run over each injection call in array order: box 0's batch, then box 1's
+    for b, o in enumerate(ors):
+        live = np.flatnonzero(o.alive == 1)
+        assert len(live) > 0
+        cols = np.array([col[gid[b][j]] for j in live])
+        assert len(cols) == len(live)
+        assert (x[:, cols] == o.positions()[:, live]).all(), f"box {b} positions"
+        assert (v[:, cols] == o.v[:, live]).all(), f"box {b} velocities"
+        assert (tg[cols] == tags[b][live]).all(), f"box {b} tags"
+    assert len(ids) == sum(int((o.alive == 1).sum()) for o in ors)
+    ctx.check()
+
+
+def test_removal_after_steps_takes_particles_beyond_their_tile_and_across_the_wrap():
+    """After a step the work list groups particles by their last half-step
+    cell, so a particle to remove may sit one cell beyond its item's tile, or
+    across the periodic wrap of the box; its n_CR, J_CR must still leave the
+    deposits exactly."""
+    _need_gpu()
+    rng = np.random.default_rng(77)
+    spec = W.BoxSpec(ndim=2, n=(16, 16, 1), dx=(1.0, 1.0, 1.0), C=20.0)
+    B, vg, rho = _fields(spec, (0.0, 0.0, 1.0), (0.0, 0.0, 0.0))
+    p = Pair(spec, ((P, P), (P, P), (P, P)), np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0),
+             np.zeros(0), B, vg, rho, capacity=3000, tile=(8, 8, 1))
+    N = 2000
+    # crowd the tile edges and the box edges, moving fast across them
+    edge = rng.choice([0.0, 7.0, 8.0, 15.0], size=(2, N)) + rng.uniform(0, 1, (2, N))
+    x = np.stack([edge[0], edge[1], np.zeros(N)])
+    v = rng.choice([-1.0, 1.0], size=(3, N)) * rng.uniform(8.0, 14.0, (3, N))
+    tags = np.where(rng.uniform(size=N) < 0.5, 0.0, 1.0)
+    p.inject(x, v, np.full(N, 1e-3), np.ones(N), tags)
+    dt = 0.05
+    for k in range(3):
+        p.step(dt, 1)
+        p.remove_tagged(0.5 if k == 1 else -1.0, 10.0)
+        p.check(f"after step {k} and removal")
+
+
 def test_injection_beyond_capacity_is_refused():
     _need_gpu()
     from paper_1412_1087_amd import mhdpic as M
