@@ -275,6 +275,39 @@ def test_injection_beyond_capacity_is_refused():
     p.check("full")
 
 
+def test_removing_every_particle_then_injecting_again():
+    """Edge cases of a changing particle count: removal of every particle
+    (deposits of n_CR, J_CR back to zero, steps of an empty store), a new
+    injection into the emptied store, a read with too small an n_max, and
+    removal refused in a context without tags."""
+    _need_gpu()
+    from paper_1412_1087_amd import mhdpic as M
+    st = W.shock_wall2d(nx=48, ny=8, front_cell=16)
+    p = Pair(st.box, st.boundary, np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), np.zeros(0),
+             st.B, st.vg, st.rho, capacity=4000, tile=(16, 16, 1))
+    p.inject(*W.shock_injection(st, 900, 0.0, seed=31))
+    p.step(st.dt, 2)
+    p.check("two steps")
+    assert p.remove_tagged(1.0, 10.0) == 900
+    p.check("all removed")
+    D = p.ctx.deposit_read().cpu().numpy()
+    assert (D[:4] == 0).all() and p.ctx.counts() == [0]
+    p.step(st.dt, 2)
+    p.check("steps of an empty store")
+    p.inject(*W.shock_injection(st, 1500, 0.5, seed=32))
+    p.step(st.dt, 1)
+    p.check("injected into the emptied store")
+    with pytest.raises(M.MhdpicError) as e:
+        p.ctx.particles_read_ids(n_max=10)
+    assert e.value.code == M.ENOMEM
+    spec = W.BoxSpec(ndim=2, n=(8, 8, 1), C=20.0)
+    q = M.Context([gpu_box(spec)], [1], to_dev(np.array([[1.5], [2.5], [0.0]])),
+                  to_dev(np.zeros((3, 1))), to_dev(np.ones(1)), to_dev(np.ones(1)))
+    with pytest.raises(M.MhdpicError) as e:
+        q.remove_tagged(1.0, 2.0)
+    assert e.value.code == M.EINVAL
+
+
 def test_position_outside_a_non_periodic_axis_rejected():
     _need_gpu()
     from paper_1412_1087_amd import mhdpic as M
