@@ -161,6 +161,11 @@ struct mhdpic_ctx {
     bool dt_uploaded = false;
     int64_t n_init = 0;   // particles given at initialisation (ids 0 .. n_init-1)
     int64_t tail = 0;     // added particles after the slots the last sort or binning filled
+    // the code words of the current buffer are those the last push wrote for
+    // this dt and n_sub (so the next call's first binning needs no rekey)
+    bool codes_fresh = false;
+    std::vector<double> codes_dt;
+    int32_t codes_nsub = 0;
     int32_t next_id = 0;  // id of the next added particle
     // cached graph of mhdpic_step_graph
     hipGraphExec_t graph_exec = nullptr;
@@ -409,6 +414,7 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
     c->cur = 1 - c->cur;
     c->it = 1 - it;
     c->tail = 0;
+    if (keys == kKeysStay) c->codes_fresh = false;  // stay codes carry no next tile
     return MHDPIC_OK;
 }
 
@@ -743,14 +749,15 @@ int set_dt(mhdpic_ctx* c, const double* dt, int32_t n_sub, hipStream_t s, bool c
 // push (n_CR, J_CR at the last sub-step only) and, except after the call's
 // last push, re-binning.
 int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double* rho,
-                  int32_t n_steps, int32_t n_sub, hipStream_t s, bool allow_timing) {
+                  int32_t n_steps, int32_t n_sub, hipStream_t s, bool allow_timing,
+                  bool codes_valid = false) {
     if (!rho) rho = B;  // never read without the Hall term
     const uint32_t saved = c->timing;
     if (!allow_timing) c->timing = 0;
     int rc;
     {
         PhaseTimer t(c, s, 0);
-        rc = launch_bin_any(c, s, kKeysRekey);
+        rc = launch_bin_any(c, s, codes_valid ? kKeysPushed : kKeysRekey);
     }
     for (int st = 0; st < n_steps && !rc; ++st) {
         {
@@ -1239,9 +1246,19 @@ int mhdpic_step_sub(mhdpic_ctx* c, const double* B, const double* vg, const doub
     c->last_stream = s;
     rc = set_dt(c, dt, n_sub, s, capturing);
     if (rc) return rc;
-    rc = enqueue_steps(c, B, vg, rho, n_steps, n_sub, s, !capturing);
+    // an eager call after a push with the same dt and n_sub bins with the
+    // codes that push wrote; a captured call is replayed in states this
+    // host code does not see, so it always recomputes them
+    const bool codes_valid = !capturing && c->codes_fresh && c->codes_nsub == n_sub &&
+                             std::equal(c->codes_dt.begin(), c->codes_dt.end(), dt) &&
+                             (int)c->codes_dt.size() == c->nb;
+    rc = enqueue_steps(c, B, vg, rho, n_steps, n_sub, s, !capturing, codes_valid);
+    c->codes_fresh = false;
     if (rc) return rc;
     if (capturing) return MHDPIC_OK;
+    c->codes_fresh = true;
+    c->codes_dt.assign(dt, dt + c->nb);
+    c->codes_nsub = n_sub;
     return post_error_copy(c, s);
 }
 
@@ -1288,7 +1305,10 @@ int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, cons
         c->graph_key = key;  // n_steps is even: the buffers end as they began
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, s));
-    if (n_steps > 0) c->tail = 0;  // its binnings took in any added particles
+    c->tail = 0;  // its binnings took in any added particles
+    c->codes_fresh = true;
+    c->codes_dt.assign(dt, dt + c->nb);
+    c->codes_nsub = n_sub;
     return post_error_copy(c, s);
 }
 
@@ -1658,6 +1678,7 @@ int mhdpic_inject(mhdpic_ctx* c, const int64_t* n_new, const double* x, const do
                        at<uint32_t>(c, L.n_items[1 - it]), L.NT);
     c->it = 1 - it;
     c->tail += total;
+    c->codes_fresh = false;  // the added particles have no code words yet
     // the new particles' n_CR, J_CR join the deposits of the state
     const DepositJob job{at<WorkItem>(c, L.tail_items), at<uint32_t>(c, L.tail_n), false, 0.0, 0.0};
     rc = launch_deposit(c, s, job);
@@ -1675,7 +1696,9 @@ int mhdpic_remove_tagged(mhdpic_ctx* c, double t_cut, double t_now, void* hip_st
     c->last_stream = s;
     const Layout& L = c->L;
     // the picked particles' n_CR, J_CR are taken back from the deposits of the
-    // state and their slots marked empty; the next binning drops them
+    // state and their slots marked empty; the next binning drops them (with
+    // codes recomputed: an empty slot takes the gone code)
+    c->codes_fresh = false;
     const DepositJob job{at<WorkItem>(c, L.items[c->it]), at<uint32_t>(c, L.n_items[c->it]), true,
                          t_cut, t_now};
     rc = launch_deposit(c, s, job);
