@@ -552,7 +552,7 @@ def run_cpu_baseline(wl, label: str, per_core: int = 65536, steps: int = 3, chec
     from oracle import oracle as O
     O.build(force=not os.path.exists(O.LIB))
     avail = sorted(os.sched_getaffinity(0))
-    P = max(1, min(16, len(avail)))  # a GPU machine's CPU share is 16 cores
+    P = max(1, min(16, len(avail)))  # at most 16 host cores (the host's share per GPU)
     rng = np.random.default_rng(11)
     # equality of the split with one process on P * check_per particles
     pick = rng.choice(wl.N, size=min(wl.N, P * check_per), replace=False)
