@@ -81,7 +81,7 @@ enum { MHDPIC_FP64 = 0, MHDPIC_FP32_MIXED = 1 };
  * deposits alike. */
 enum { MHDPIC_PERIODIC = 0, MHDPIC_REFLECT = 1, MHDPIC_ABSORB = 2 };
 
-/* One periodic box of the grid (units: the paper's code units, Sec. 5). */
+/* One box of the grid (units: the paper's code units, Sec. 5). */
 typedef struct {
     int32_t ndim;           /* 2 or 3; every box of one context has the same ndim */
     int32_t n[3];           /* cells per dimension; n[2] must be 1 in 2D.
