@@ -78,15 +78,18 @@ def make_workload(name: str):
     return wl, label
 
 
-def algorithmic_bytes(ndim: int, N: int, NC: int, fsz: int = 8, msz: int = 8) -> dict:
+def algorithmic_bytes(ndim: int, N: int, NC: int, fsz: int = 8, msz: int = 8,
+                      moves_in_push: bool = False) -> dict:
     """Bytes the fused push kernel must move per launch.
 
     Per particle: read cell index (4), offsets (ndim*fsz), four-velocity
     (3*fsz), m and q/mc (2*msz); write cell index, offsets, four-velocity.
+    When the push also moves the particles to their new slots, it reads the
+    slot map (4) and writes m and q/mc (2*msz) as well.
     Per cell: read E and B (6*fsz), read+write the accumulated -dM, -dE_k
     (2*32), write n_CR, J_CR (32)."""
-    p_read = 4 + ndim * fsz + 3 * fsz + 2 * msz
-    p_write = 4 + ndim * fsz + 3 * fsz
+    p_read = 4 + ndim * fsz + 3 * fsz + 2 * msz + (4 if moves_in_push else 0)
+    p_write = 4 + ndim * fsz + 3 * fsz + (2 * msz if moves_in_push else 0)
     c_bytes = 6 * fsz + 64 + 32
     return dict(per_particle=p_read + p_write, per_cell=c_bytes,
                 per_launch=N * (p_read + p_write) + NC * c_bytes)
@@ -96,7 +99,14 @@ def algorithmic_bytes(ndim: int, N: int, NC: int, fsz: int = 8, msz: int = 8) ->
 # GPU leg
 # --------------------------------------------------------------------------
 
-def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), precision=0):
+def moves_in_push(ndim: int, moves: int) -> bool:
+    """Whether the push moves the particles (the library's automatic choice:
+    in 3D)."""
+    return moves == 2 or (moves == 0 and ndim == 3)
+
+
+def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), precision=0,
+            moves=0):
     import torch
     from paper_1412_1087_amd import mhdpic as M
 
@@ -123,6 +133,8 @@ def run_gpu(wl, steps: int, warmup: int, calibrate_copy: bool, tile=(0, 0, 0), p
     ctx = M.Context([box], [wl.N], xs, vs, ms_, qs, precision=precision)
     torch.cuda.synchronize()
     init_ms = 1e3 * (time.perf_counter() - t_init)
+    if moves:
+        ctx.set_particle_moves(moves)
     del xs, vs, ms_, qs
     log(f"init done: N={wl.N} cells={box.n_cells}, context creation {init_ms:.1f} ms")
     if warmup > 0:
@@ -394,7 +406,7 @@ def run_precision_form(steps: int, warmup: int):
     out["fp64_value"] = round(wl.N * steps / (ms64 * 1e-3), 1)
     out["value"] = round(wl.N * steps / (ms32 * 1e-3), 1)
     out["speedup_vs_fp64"] = round(ms64 / ms32, 3)
-    alg = algorithmic_bytes(3, wl.N, box.n_cells, fsz=4, msz=4)
+    alg = algorithmic_bytes(3, wl.N, box.n_cells, fsz=4, msz=4, moves_in_push=moves_in_push(3, 0))
     out["hbm_frac_whole_step"] = round(alg["per_launch"] / (ms32 * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)
     log(f"precision form: fp32 {out['value']:.4g}/s, fp64 {out['fp64_value']:.4g}/s, err {err}")
     return out
@@ -597,6 +609,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="bell3d")
     ap.add_argument("--tile", default="0,0,0")
+    ap.add_argument("--moves", choices=("auto", "binning", "push"), default="auto",
+                    help="where the particles move to their new slots (library default: auto)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="fp32: the precision form on the chosen workload (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
@@ -642,16 +656,20 @@ def main():
     # the oracle's processes are forked before this process touches the GPU
     cpu = None if args.no_cpu else run_cpu_baseline(wl, label)
     prec = 1 if args.precision == "fp32" else 0
-    g = run_gpu(wl, args.steps, args.warmup, args.calibrate_copy, tile=tile, precision=prec)
+    moves = {"auto": 0, "binning": 1, "push": 2}[args.moves]
+    g = run_gpu(wl, args.steps, args.warmup, args.calibrate_copy, tile=tile, precision=prec,
+                moves=moves)
     N = wl.N
     ms = g["ms"]
     value = N * args.steps / (ms * 1e-3)
     push_ms, push_n = g["push"]
     fsz = 4 if prec else 8
-    alg = algorithmic_bytes(wl.box.ndim, N, g["n_cells"], fsz=fsz, msz=fsz)
+    mip = moves_in_push(wl.box.ndim, moves)
+    alg = algorithmic_bytes(wl.box.ndim, N, g["n_cells"], fsz=fsz, msz=fsz, moves_in_push=mip)
     push_avg_s = push_ms * 1e-3 / max(push_n, 1)
     achieved = alg["per_launch"] / push_avg_s / 1e9
-    traffic = load_traffic(label + ("/fp32" if prec else ""), alg["per_launch"])
+    traffic = load_traffic(label + ("/fp32" if prec else "") + (f"/moves-{args.moves}" if moves else ""),
+                           alg["per_launch"])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel="k_push_f32" if prec else "k_push_f64",
@@ -689,7 +707,8 @@ def main():
         "data": DATA_NOTE.get(args.workload, "synthetic (seeded)"),
         "config": {"workload": label, "cells": g["n_cells"], "particles": N, "ndim": wl.box.ndim,
                    "hall": wl.box.hall, "C": wl.box.C, "dt": wl.dt, "tile": list(tile),
-                   "precision": args.precision},
+                   "precision": args.precision,
+                   "particle_moves": "in_push" if mip else "in_binning"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases_ms_instrumented_pass": phases,

@@ -305,10 +305,16 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
 // particles are moved one array at a time through LDS (MoveMap, move_step).
 // TAGGED: the context carries particle tags (binary64), moved last; the
 // staging buffer is then 8 bytes per particle in both precisions.
-template <int NDIM, typename PS, int BLOCK, bool TAGGED>
+// MAP: only the ids (and tags) are moved; the kernel writes, for every
+// destination slot, the slot its particle has in A, and the next push reads
+// the particle there and stores it, updated, at the destination (the push
+// reads and writes every particle anyway, so the other arrays need no move
+// of their own).
+template <int NDIM, typename PS, int BLOCK, bool TAGGED, bool MAP>
 __global__ void __launch_bounds__(BLOCK)
 k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
-                    const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items) {
+                    const WorkItem* __restrict__ items, const uint32_t* __restrict__ n_items,
+                    uint32_t* __restrict__ map) {
     constexpr int K = Codes<NDIM>::K;
     constexpr int STAY = Codes<NDIM>::STAY;
     constexpr int NCL = K;        // shift classes (3^NDIM)
@@ -356,8 +362,12 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     ItemRegs<BLOCK, uint32_t> rcell;
     ItemRegs<BLOCK, int32_t> rpid;
     ItemRegs<BLOCK, R> rbuf[2];
-    rcell.load(A.cell, mm);
-    rbuf[0].load(rsrc[0], mm);
+    if (MAP) {
+        rpid.load(A.pid, mm);
+    } else {
+        rcell.load(A.cell, mm);
+        rbuf[0].load(rsrc[0], mm);
+    }
     for (int c = threadIdx.x; c < NG * RS; c += BLOCK) s_n[c] = 0;
     __syncthreads();
 #pragma unroll
@@ -417,6 +427,22 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         s_grp[s_lbase[g] + pos] = (uint8_t)g;
     }
     __syncthreads();
+    if (MAP) {
+        constexpr int UD = kItemParticles / BLOCK;
+#pragma unroll
+        for (int u = 0; u < UD; ++u) {
+            const int L = threadIdx.x + u * BLOCK;
+            if (L < mm.nd) map[mm.goff[mm.grp[L]] + (uint32_t)L] = (uint32_t)mm.begin + mm.from[L];
+        }
+        if (TAGGED) {
+            ItemRegs<BLOCK, double> rtag;
+            move_step<BLOCK>(rpid, Bo.pid, s_stage, rtag, (const double*)A.tag, mm);
+            move_step<BLOCK>(rtag, Bo.tag, s_stage, rcell, (const uint32_t*)nullptr, mm);
+        } else {
+            move_step<BLOCK>(rpid, Bo.pid, s_stage, rcell, (const uint32_t*)nullptr, mm);
+        }
+        return;
+    }
     // the arrays one after another, through LDS, in destination order, with
     // two arrays in flight: array q+2 is loaded while array q is stored
     move_step<BLOCK>(rcell, Bo.cell, s_stage, rbuf[1], rsrc[1], mm);

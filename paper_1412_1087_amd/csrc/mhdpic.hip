@@ -117,9 +117,10 @@ struct GraphKey {
     int32_t n_steps = 0, n_sub = 1;
     std::vector<double> dt;
     int cur = 0, it = 0, nj = 0;
+    int32_t moves = 0;
     bool operator==(const GraphKey& o) const {
         return B == o.B && vg == o.vg && rho == o.rho && n_steps == o.n_steps && n_sub == o.n_sub &&
-               dt == o.dt && cur == o.cur && it == o.it && nj == o.nj;
+               dt == o.dt && cur == o.cur && it == o.it && nj == o.nj && moves == o.moves;
     }
 };
 
@@ -144,6 +145,15 @@ struct mhdpic_ctx {
     Layout L;
     unsigned char* ws = nullptr;
     int cur = 0;   // which particle buffer (0 = A, 1 = B) holds the state
+    // a binning has left the map from the other buffer's slots to the
+    // current one's, and the push that reads it has not run yet
+    bool map_pending = false;
+    // where the particles of a step move to their new slots
+    // (mhdpic_set_particle_moves); automatic: in the push for 3D boxes
+    int32_t moves = MHDPIC_MOVES_AUTO;
+    bool moves_in_push() const {
+        return moves == MHDPIC_MOVES_IN_PUSH || (moves == MHDPIC_MOVES_AUTO && ndim == 3);
+    }
     int it = 0;    // which work list describes that buffer
     int nj = 0;    // which nJ buffer is current
     hipStream_t last_stream = nullptr;
@@ -403,15 +413,22 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
                        at<int32_t>(c, L.tile_box), bd, at<uint32_t>(c, L.start),
                        at<uint32_t>(c, L.item_first[1 - it]), at<WorkItem>(c, L.items[1 - it]),
                        L.NT, kItemParticles);
-    if (L.tagged)
-        hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256, true>), dim3(item_grid(L)), dim3(256), 0, s,
-                           A, Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
-                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
+    // where the particles move (mhdpic_set_particle_moves): in the push, the
+    // binning moves only the ids (and tags) and leaves the map from new slots
+    // to old ones, through which the push reads the particles and writes them,
+    // updated, to the other buffer; a compaction always moves them itself
+    const bool map = keys != kKeysStay && c->moves_in_push();
+    auto kern = L.tagged ? (map ? k_bin_scatter_class<NDIM, PS, 256, true, true>
+                                : k_bin_scatter_class<NDIM, PS, 256, true, false>)
+                         : (map ? k_bin_scatter_class<NDIM, PS, 256, false, true>
+                                : k_bin_scatter_class<NDIM, PS, 256, false, false>);
+    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(256), 0, s, A, Bo, at<uint16_t>(c, L.code),
+                       at<uint32_t>(c, L.off), at<WorkItem>(c, L.items[it]),
+                       at<uint32_t>(c, L.n_items[it]), at<uint32_t>(c, L.key));
+    if (map)
+        c->map_pending = true;
     else
-        hipLaunchKernelGGL((k_bin_scatter_class<NDIM, PS, 256, false>), dim3(item_grid(L)), dim3(256), 0, s,
-                           A, Bo, at<uint16_t>(c, L.code), at<uint32_t>(c, L.off),
-                           at<WorkItem>(c, L.items[it]), at<uint32_t>(c, L.n_items[it]));
-    c->cur = 1 - c->cur;
+        c->cur = 1 - c->cur;
     c->it = 1 - it;
     c->tail = 0;
     if (keys == kKeysStay) c->codes_fresh = false;  // stay codes carry no next tile
@@ -506,7 +523,9 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred, int grp) {
     using R = typename Pol::R;
     const Layout& L = c->L;
     PushArgsT<Pol> a;
-    a.P = part<typename Pol::Part, R>(c, c->cur);
+    a.Psrc = part<typename Pol::Part, R>(c, c->cur);
+    a.map = c->map_pending ? at<uint32_t>(c, L.key) : nullptr;
+    a.P = part<typename Pol::Part, R>(c, c->map_pending ? 1 - c->cur : c->cur);
     a.code = at<uint16_t>(c, L.code);
     a.cnt = at<uint32_t>(c, L.cnt);
     a.EB = at<R>(c, L.EB);
@@ -613,8 +632,20 @@ int launch_init_deposit(mhdpic_ctx* c, hipStream_t s) {
     return launch_deposit(c, s, job);
 }
 
-int launch_push(mhdpic_ctx* c, hipStream_t s, bool p) {
+int launch_push_groups(mhdpic_ctx* c, hipStream_t s, bool p) {
     MHDPIC_TILE_DISPATCH(launch_push_t, c, s, p);
+}
+
+// The push of every launch group; after a binning that left a map it moves
+// the particles into the other buffer.
+int launch_push(mhdpic_ctx* c, hipStream_t s, bool p) {
+    const int rc = launch_push_groups(c, s, p);
+    if (rc) return rc;
+    if (c->map_pending) {
+        c->map_pending = false;
+        c->cur = 1 - c->cur;
+    }
+    return MHDPIC_OK;
 }
 
 int launch_bin_any(mhdpic_ctx* c, hipStream_t s, int keys) {
@@ -781,6 +812,10 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
         c->nj = 1 - c->nj;
     }
     c->timing = saved;
+    if (rc && c->map_pending) {  // the particles never left the current buffer
+        c->it = 1 - c->it;
+        c->map_pending = false;
+    }
     if (rc) return rc;
     HIP_TRY(hipGetLastError());
     return MHDPIC_OK;
@@ -1281,7 +1316,8 @@ int mhdpic_step_graph_sub(mhdpic_ctx* c, const double* B, const double* vg, cons
     // them to this dt first (a no-op when they are current)
     rc = set_dt(c, dt, n_sub, s, false);
     if (rc) return rc;
-    GraphKey key{B, vg, rho, n_steps, n_sub, std::vector<double>(dt, dt + c->nb), c->cur, c->it, c->nj};
+    GraphKey key{B, vg, rho, n_steps, n_sub, std::vector<double>(dt, dt + c->nb), c->cur, c->it, c->nj,
+                 c->moves};
     if (!c->graph_exec || !(c->graph_key == key)) {
         if (c->graph_exec) {
             HIP_TRY(hipGraphExecDestroy(c->graph_exec));
@@ -1717,6 +1753,14 @@ int mhdpic_check(mhdpic_ctx* c, void* hip_stream) {
     fill_u32(at<uint32_t>(c, c->L.err), 1, 0u, s);
     HIP_TRY(hipStreamSynchronize(s));
     if (bits) return fail(code_of(bits), msg_of(bits));
+    return MHDPIC_OK;
+}
+
+int mhdpic_set_particle_moves(mhdpic_ctx* c, int32_t where) {
+    if (!c) return fail(MHDPIC_EINVAL, "ctx is NULL");
+    if (where != MHDPIC_MOVES_AUTO && where != MHDPIC_MOVES_IN_BINNING && where != MHDPIC_MOVES_IN_PUSH)
+        return fail(MHDPIC_EINVAL, "unknown particle move setting");
+    c->moves = where;
     return MHDPIC_OK;
 }
 

@@ -22,7 +22,10 @@ namespace mhdpic {
 
 template <class Pol>
 struct PushArgsT {
-    typename Pol::Part P;        // tile-sorted particles, updated in place
+    typename Pol::Part Psrc;     // the particles before this push
+    const uint32_t* map;         // slot j of P -> slot of its particle in Psrc; NULL:
+                                 // Psrc is P and the particles are updated in place
+    typename Pol::Part P;        // out: tile-sorted particles (the ids already there)
     uint16_t* code;              // out: code word (pack_code)
     uint32_t* cnt;               // out: [item][code] particle counts
     const typename Pol::R* EB;   // [cells][6] E and B
@@ -191,14 +194,16 @@ __device__ __forceinline__ void field_store(float* F, int NFF, int c, const floa
     }
 }
 
-// One particle's stored state (in 2D the third offset reads as 0).
+// One particle's stored state (in 2D the third offset reads as 0), read for
+// slot jd from the slot the binning's map names, if it left one.
 template <int NDIM, typename R>
 struct PartRec {
     uint32_t cell = 0;
     R d[3] = {R(0), R(0), R(0)}, v[3] = {R(0), R(0), R(0)};
     R m = R(0), qm = R(0);
     template <typename PS>
-    __device__ __forceinline__ void load(const PS& P, int j) {
+    __device__ __forceinline__ void load(const PS& P, const uint32_t* map, int jd) {
+        const int j = map ? (int)map[jd] : jd;
         cell = P.cell[j];
         d[0] = P.d[0][j];
         d[1] = P.d[1][j];
@@ -277,14 +282,14 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     // have no registers to spare for it
     constexpr bool kPrefetch = PushShape<Pol, NDIM>::PREFETCH;
     PartRec<NDIM, R> nxt;
-    if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.P, w.begin + (int)threadIdx.x);
+    if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.Psrc, a.map, w.begin + (int)threadIdx.x);
     for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
         PartRec<NDIM, R> cur;
         if (kPrefetch) {
             cur = nxt;
-            if (j + BLOCK < w.end) nxt.load(a.P, j + BLOCK);
+            if (j + BLOCK < w.end) nxt.load(a.Psrc, a.map, j + BLOCK);
         } else {
-            cur.load(a.P, j);
+            cur.load(a.Psrc, a.map, j);
         }
         int i[3];
         unpack_cell<NDIM>(cur.cell, i[0], i[1], i[2]);
@@ -424,7 +429,8 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
             }
         }
 
-        // store x^(n+1), v^(n+1) (a particle that left keeps only its mark)
+        // store x^(n+1), v^(n+1) and the particle's constants at its slot (a
+        // particle that left keeps only its mark)
         a.P.cell[j] = gone ? kDeadCell : pack_cell<NDIM>(i[0], i[1], i[2]);
         a.P.d[0][j] = dl[0];
         a.P.d[1][j] = dl[1];
@@ -432,6 +438,10 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
         a.P.v[0][j] = vn[0];
         a.P.v[1][j] = vn[1];
         a.P.v[2][j] = vn[2];
+        if (a.map) {
+            a.P.m[j] = cur.m;
+            a.P.qm[j] = cur.qm;
+        }
 
         // tile and bank residue of the next half-step cell (the operations of
         // the next step's first drift), or the gone code if that drift takes

@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("MHDPIC_LIB") or os.path.join(HERE, "libmhdpic.so")
 OK, EINVAL, ENOMEM, EDEVICE, ERANGE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
 PERIODIC, REFLECT, ABSORB = 0, 1, 2
+MOVES_AUTO, MOVES_IN_BINNING, MOVES_IN_PUSH = 0, 1, 2
 
 EXPORTED = [
     "mhdpic_workspace_size", "mhdpic_init", "mhdpic_step", "mhdpic_deposit_read",
@@ -28,7 +29,7 @@ EXPORTED = [
     "mhdpic_step_graph", "mhdpic_autotune_workspace_size", "mhdpic_autotune", "mhdpic_step_sub",
     "mhdpic_feedback", "mhdpic_step_graph_sub", "mhdpic_advance", "mhdpic_advance_noalloc",
     "mhdpic_particles_read_ids", "mhdpic_counts", "mhdpic_inject", "mhdpic_remove_tagged",
-    "mhdpic_autotune_classes_workspace_size", "mhdpic_autotune_classes",
+    "mhdpic_autotune_classes_workspace_size", "mhdpic_autotune_classes", "mhdpic_set_particle_moves",
 ]
 
 
@@ -93,6 +94,8 @@ def lib():
         L.mhdpic_last_error.argtypes = []
         L.mhdpic_timing_enable.restype = ct.c_int
         L.mhdpic_timing_enable.argtypes = [vp, ct.c_int32]
+        L.mhdpic_set_particle_moves.restype = ct.c_int
+        L.mhdpic_set_particle_moves.argtypes = [vp, ct.c_int32]
         L.mhdpic_timing_read.restype = ct.c_int
         L.mhdpic_timing_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
         L.mhdpic_step_graph.restype = ct.c_int
@@ -314,6 +317,11 @@ class Context:
     def remove_tagged(self, t_cut: float, t_now: float, stream=None):
         """Removes particles with tag < t_cut once t_now >= 2 tag (Sec. 5)."""
         _check(lib().mhdpic_remove_tagged(self._h, float(t_cut), float(t_now), _stream(stream)))
+
+    def set_particle_moves(self, where: int):
+        """Where a step moves the particles to their new slots: MOVES_AUTO,
+        MOVES_IN_BINNING or MOVES_IN_PUSH (same results, different cost)."""
+        _check(lib().mhdpic_set_particle_moves(self._h, int(where)))
 
     PHASES = ("bin", "fieldprep", "push", "clear")
 

@@ -33,7 +33,7 @@ def to_dev(a: np.ndarray, dev="cuda"):
 class DeviceRun:
     """One or more workloads as the boxes of one GPU context."""
 
-    def __init__(self, wls, tile=(0, 0, 0), precision=0):
+    def __init__(self, wls, tile=(0, 0, 0), precision=0, moves=0):
         import torch
         from paper_1412_1087_amd import mhdpic as M
         if not isinstance(wls, (list, tuple)):
@@ -51,6 +51,8 @@ class DeviceRun:
         self.rho = to_dev(np.concatenate([w.rho for w in self.wls]))
         self.ctx = M.Context(self.boxes, [w.N for w in self.wls], to_dev(x), to_dev(v), to_dev(m),
                              to_dev(qm), precision=precision)
+        if moves:
+            self.ctx.set_particle_moves(moves)
         self.cell_off = np.cumsum([0] + [w.box.n_cells for w in self.wls])
         self.part_off = np.cumsum([0] + [w.N for w in self.wls])
         torch.cuda.synchronize()

@@ -233,3 +233,31 @@ def test_user_captured_step_replays_match_the_oracle():
         o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
         (D,) = g.deposits()
         assert (D == o.D).all(), f"eager after replay {rep}"
+
+
+@pytest.mark.parametrize("moves", [1, 2], ids=["in_binning", "in_push"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_graph_replays_match_eager_for_both_move_settings(moves, dim):
+    _need_gpu()
+    wls = _boxes(n=6, seed0=1700) if dim == 2 else [W.bell3d(n=(13, 9, 6), ppc=3, seed=1701, hall=1)]
+    eager = DeviceRun(wls, moves=moves)
+    graph = DeviceRun(wls, moves=moves)
+    oracles = [oracle_run(w) for w in wls]
+    stream = torch.cuda.Stream()
+    dts = [w.dt for w in wls]
+    for rep in range(3):
+        eager.step(2, dts=dts)
+        with torch.cuda.stream(stream):
+            graph.ctx.step_graph(graph.B, graph.vg, graph.rho, dts, 2, stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for w, o in zip(wls, oracles):
+            o.step(w.B, w.vg, w.rho, w.dt, 2)
+        De, Dg = eager.deposits(), graph.deposits()
+        pe, pg = eager.particles(), graph.particles()
+        for b, o in enumerate(oracles):
+            assert (De[b] == o.D).all(), f"replay {rep}: box {b} eager != oracle"
+            assert (Dg[b] == o.D).all(), f"replay {rep}: box {b} graph != oracle"
+            assert_states_exact(pg[b][0], pg[b][1], o.positions(), o.v, f"box {b}")
+    eager.ctx.check()
+    graph.ctx.check()

@@ -30,13 +30,15 @@ class Pair:
     """One box run by the library and by the oracle from the same inputs."""
 
     def __init__(self, spec, boundary, x, v, m, qm, B, vg, rho, capacity=0, precision=0,
-                 tile=(0, 0, 0)):
+                 tile=(0, 0, 0), moves=0):
         from paper_1412_1087_amd import mhdpic as M
         self.spec = spec
         self.B, self.vg, self.rho = B, vg, rho
         self.dB, self.dvg, self.drho = to_dev(B), to_dev(vg), to_dev(rho)
         self.ctx = M.Context([gpu_box(spec, tile, boundary, capacity)], [x.shape[1]], to_dev(x),
                              to_dev(v), to_dev(m), to_dev(qm), precision=precision)
+        if moves:
+            self.ctx.set_particle_moves(moves)
         self.o = O.System(oracle_box(spec, boundary), x, v, m, qm)
         self.tags = np.full(x.shape[1], np.inf)
         torch.cuda.synchronize()
@@ -121,15 +123,16 @@ def test_faces_3d_hall_tiles_and_subcycling_match_oracle():
     p.check("3 more steps")
 
 
+@pytest.mark.parametrize("moves", [1, 2], ids=["moves_in_binning", "moves_in_push"])
 @pytest.mark.parametrize("precision", [0])
-def test_shock_injection_and_removal_match_oracle(precision):
+def test_shock_injection_and_removal_match_oracle(precision, moves):
     """The Sec. 5 loop at test size: CRs injected at the moving front every
     step, tagged with their injection time, a reflecting wall and an inflow
     face, and removal of early particles at twice their injection time."""
     _need_gpu()
     st = W.shock_wall2d(nx=64, ny=8, front_cell=24)
     p = Pair(st.box, st.boundary, np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), np.zeros(0),
-             st.B, st.vg, st.rho, capacity=20000, precision=precision)
+             st.B, st.vg, st.rho, capacity=20000, precision=precision, moves=moves)
     t = 0.0
     removed = 0
     for k in range(12):
@@ -146,14 +149,15 @@ def test_shock_injection_and_removal_match_oracle(precision):
     p.check("end")
 
 
-def test_stacked_injections_removal_and_compaction_match_oracle():
+@pytest.mark.parametrize("moves", [1, 2], ids=["moves_in_binning", "moves_in_push"])
+def test_stacked_injections_removal_and_compaction_match_oracle(moves):
     """Several injections between two steps (each one a sorted tail of its
     own), a removal whose slots a later injection needs (the library then
     compacts the store first), and graph-captured steps after injection."""
     _need_gpu()
     st = W.shock_wall2d(nx=64, ny=8, front_cell=24)
     p = Pair(st.box, st.boundary, np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), np.zeros(0),
-             st.B, st.vg, st.rho, capacity=2600)
+             st.B, st.vg, st.rho, capacity=2600, moves=moves)
     for k in range(3):
         p.inject(*W.shock_injection(st, 700, 0.1 * k, seed=950 + k))
     p.check("three stacked tails")

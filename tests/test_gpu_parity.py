@@ -35,9 +35,9 @@ def _assert_states(wl, sysO, x_g, v_g):
                             f"{tuple(badv[0])}: {v_g[tuple(badv[0])]!r} vs {vo[tuple(badv[0])]!r}")
 
 
-def _parity(wl, n_steps=1, tile=(0, 0, 0), steps_per_call=1):
+def _parity(wl, n_steps=1, tile=(0, 0, 0), steps_per_call=1, moves=0):
     _need_gpu()
-    g = DeviceRun(wl, tile=tile)
+    g = DeviceRun(wl, tile=tile, moves=moves)
     o = oracle_run(wl)
     (D0,) = g.deposits()
     assert (D0 == o.D).all(), "init deposit differs"
@@ -341,3 +341,63 @@ def test_position_too_far_from_origin_rejected_at_init():
     with pytest.raises(M.MhdpicError) as e:
         DeviceRun(wl)
     assert e.value.code == M.ERANGE
+
+
+# ---------------------------------------------------------------------------
+# the particles moved to their new slots by the binning or by the push
+# ---------------------------------------------------------------------------
+
+MOVES = [pytest.param(1, id="in_binning"), pytest.param(2, id="in_push")]
+
+
+@pytest.mark.parametrize("moves", MOVES)
+def test_parity_moves_2d_many_steps(moves):
+    # relativistic isotropic particles crossing tiles every few steps
+    _parity(W.shock2d(nx=256, ny=32, n_particles=256 * 32 * 4, seed=60), n_steps=12,
+            steps_per_call=4, moves=moves)
+
+
+@pytest.mark.parametrize("moves", MOVES)
+def test_parity_moves_3d_hall_ragged(moves):
+    _parity(W.bell3d(n=(13, 9, 6), ppc=3, seed=61, hall=1), n_steps=4, steps_per_call=2,
+            moves=moves)
+
+
+@pytest.mark.parametrize("moves", MOVES)
+def test_parity_moves_3d_tiles_and_subcycling(moves):
+    _need_gpu()
+    wl = W.bell3d(n=(11, 10, 9), ppc=2, seed=62)
+    g = DeviceRun(wl, tile=(4, 4, 4), moves=moves)
+    o = oracle_run(wl)
+    for _ in range(2):
+        g.step(2, n_sub=3)
+        o.step(wl.B, wl.vg, wl.rho, wl.dt, 2, n_sub=3)
+    (D,) = g.deposits()
+    assert (D == o.D).all()
+    ((x, v),) = g.particles()
+    _assert_states(wl, o, x, v)
+    g.ctx.check()
+
+
+def test_parity_moves_switched_between_calls():
+    _need_gpu()
+    for wl in (W.gyro2d(nx=37, ny=23, ppc=5, seed=63), W.bell3d(n=(13, 9, 6), ppc=3, seed=64)):
+        g = DeviceRun(wl)
+        o = oracle_run(wl)
+        for moves in (2, 1, 0, 2, 2, 1):
+            g.ctx.set_particle_moves(moves)
+            g.step(2)
+            o.step(wl.B, wl.vg, wl.rho, wl.dt, 2)
+            (D,) = g.deposits()
+            assert (D == o.D).all(), f"moves {moves}"
+            ((x, v),) = g.particles()
+            _assert_states(wl, o, x, v)
+        g.ctx.check()
+
+
+def test_particle_moves_rejects_unknown_setting():
+    _need_gpu()
+    from paper_1412_1087_amd import mhdpic as M
+    g = DeviceRun(W.gyro2d(nx=8, ny=8, ppc=2, seed=65))
+    with pytest.raises(M.MhdpicError):
+        g.ctx.set_particle_moves(3)
