@@ -349,18 +349,16 @@ int mhdpic_timing_read(mhdpic_ctx* ctx, double* ms, int64_t* launches);
 
 /* Where the particles of a step move to their new slots.  Before each push
  * the particles are binned by the tile of the cell they have reached.
+ *   MHDPIC_MOVES_IN_PUSH: the binning moves only the ids (and tags) and
+ *     leaves a map from new slots to old ones; the push reads each particle
+ *     through it and writes it, updated, to its new slot.  This saves a pass
+ *     over the particle data, but the push's reads become gathers, whose
+ *     cost grows the more the particles of a tile change cells in different
+ *     ways from one step to the next;
  *   MHDPIC_MOVES_IN_BINNING: the binning moves every particle to its slot in
  *     the other particle buffer (a read and a write of all its data), and the
  *     push updates the particles in place;
- *   MHDPIC_MOVES_IN_PUSH: the binning moves only the ids (and tags) and
- *     leaves a map from new slots to old ones; the push reads each particle
- *     through it and writes it, updated, to its new slot.  This saves the
- *     binning's pass over the particle data, but the push's reads become
- *     gathers, which cost more the more the particles of a tile change cells
- *     in different ways from one step to the next (isotropic relativistic
- *     particles do; a drifting beam does not);
- *   MHDPIC_MOVES_AUTO (the default): in the push for 3D boxes, in the
- *     binning for 2D boxes.
+ *   MHDPIC_MOVES_AUTO (the default): in the push.
  * Positions, velocities and deposits are the same either way, bit for bit.
  * Takes effect at the next step call.  EINVAL for another value. */
 enum { MHDPIC_MOVES_AUTO = 0, MHDPIC_MOVES_IN_BINNING = 1, MHDPIC_MOVES_IN_PUSH = 2 };

@@ -289,6 +289,13 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
     __syncthreads();
 }
 
+// Source slots per chunk of the level order of a 2D binning whose push reads
+// the particles through the map (a power of two dividing kItemParticles).
+#ifndef MHDPIC_MAP_CHUNK_2D
+#define MHDPIC_MAP_CHUNK_2D 256
+#endif
+constexpr int kMapChunk2D = MHDPIC_MAP_CHUNK_2D;
+
 // Moves the particles of each current work item to their groups' offsets.
 //
 // Order within a group (the particles of one item with one direction code):
@@ -309,7 +316,14 @@ __device__ __forceinline__ void move_step(const ItemRegs<BLOCK, TC>& cur, TC* __
 // destination slot, the slot its particle has in A, and the next push reads
 // the particle there and stores it, updated, at the destination (the push
 // reads and writes every particle anyway, so the other arrays need no move
-// of their own).
+// of their own).  The push's reads are then gathers, and a level order over
+// a whole group of isotropic particles, whose residues change at random from
+// step to step, draws the 64 particles of a wave from some 26 lines of
+// 16 slots (a random walk of the residue counts); in 2D the levels therefore
+// run over chunks of kMapChunk2D source slots, without the stay classes,
+// which brings it to about 10 lines for a few more same-residue lanes.  The
+// particles of the 3D boxes (drifting beams) keep their order from step to
+// step well enough, and there the stay classes pay for themselves.
 template <int NDIM, typename PS, int BLOCK, bool TAGGED, bool MAP>
 __global__ void __launch_bounds__(BLOCK)
 k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32_t* __restrict__ off,
@@ -320,11 +334,18 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
     constexpr int NCL = K;        // shift classes (3^NDIM)
     constexpr int NG = NCL + K;   // groups: stay classes, then moving codes
     constexpr int RS = kResidues;
-    __shared__ uint32_t s_n[NG * RS];
+    // levels run over a whole group, or over each chunk of CH source slots
+    // of it (then without stay classes) when a 2D push reads through the map
+    constexpr int CH = (MAP && NDIM == 2) ? kMapChunk2D : kItemParticles;
+    constexpr int NCH = kItemParticles / CH;
+    constexpr bool CLASSES = NCH == 1;
+    __shared__ uint32_t s_n[NCH * NG * RS];
+    __shared__ uint32_t s_cb[NCH * NG];  // slots of the group's earlier chunks
     __shared__ uint32_t s_off[NG], s_lbase[NG], s_nd;
     __shared__ uint16_t s_src[kItemParticles];
     __shared__ uint8_t s_grp[kItemParticles];
-    using SR = typename std::conditional<TAGGED, double, typename PS::R>::type;
+    using SR = typename std::conditional<
+        TAGGED, double, typename std::conditional<MAP, uint32_t, typename PS::R>::type>::type;
     __shared__ SR s_stage[kItemParticles];
     uint32_t* s_key = reinterpret_cast<uint32_t*>(s_stage);  // ranks, until the moves
     uint32_t item;
@@ -368,7 +389,7 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         rcell.load(A.cell, mm);
         rbuf[0].load(rsrc[0], mm);
     }
-    for (int c = threadIdx.x; c < NG * RS; c += BLOCK) s_n[c] = 0;
+    for (int c = threadIdx.x; c < NCH * NG * RS; c += BLOCK) s_n[c] = 0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -379,22 +400,42 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
                 s_key[L] = 0xFFFFFFFFu;
                 continue;
             }
-            const int g = k == STAY ? code_class(cr[u]) : NCL + k;
-            const uint32_t r = atomicAdd(&s_n[g * RS + b], 1u);
-            s_key[L] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16);
+            const int c = NCH > 1 ? L / CH : 0;
+            const int g = k == STAY ? (CLASSES ? code_class(cr[u]) : 0) : NCL + k;
+            const uint32_t r = atomicAdd(&s_n[(c * NG + g) * RS + b], 1u);
+            s_key[L] = r | ((uint32_t)b << 12) | ((uint32_t)g << 16) | ((uint32_t)c << 22);
         }
     }
     __syncthreads();
+    if (NCH > 1) {  // particles of each (chunk, group)
+        for (int t = threadIdx.x; t < NCH * NG; t += BLOCK) {
+            uint32_t n = 0;
+#pragma unroll
+            for (int b = 0; b < RS; ++b) n += s_n[t * RS + b];
+            s_cb[t] = n;
+        }
+        __syncthreads();
+    }
     // group bases: the stay classes in class order from the stay group's
     // offset, the moving groups at their own offsets; lane g of the first
-    // wave scans the group sizes
+    // wave scans the group sizes (and turns its chunk counts into bases)
     static_assert(NG <= 64, "one lane per group");
+    static_assert(NCH <= 64 && CH <= 4096, "chunk and rank fields of the key");
     if (threadIdx.x < 64) {
         const int g = threadIdx.x;
         uint32_t t = 0;
-        if (g < NG)
+        if (g < NG) {
+            if (NCH > 1) {
+                for (int c = 0; c < NCH; ++c) {
+                    const uint32_t n = s_cb[c * NG + g];
+                    s_cb[c * NG + g] = t;
+                    t += n;
+                }
+            } else {
 #pragma unroll
-            for (int b = 0; b < RS; ++b) t += s_n[g * RS + b];
+                for (int b = 0; b < RS; ++b) t += s_n[g * RS + b];
+            }
+        }
         uint32_t x = t;  // inclusive scan over the lanes
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o);
@@ -415,9 +456,9 @@ k_bin_scatter_class(PS A, PS Bo, const uint16_t* __restrict__ code, const uint32
         const uint32_t key = s_key[j - w.begin];
         if (key == 0xFFFFFFFFu) continue;
         const uint32_t r = key & 4095u;
-        const int b = (int)((key >> 12) & 15u), g = (int)(key >> 16);
-        const uint32_t* nk = s_n + g * RS;
-        uint32_t pos = 0;
+        const int b = (int)((key >> 12) & 15u), g = (int)((key >> 16) & 63u), c = (int)(key >> 22);
+        const uint32_t* nk = s_n + (c * NG + g) * RS;
+        uint32_t pos = NCH > 1 ? s_cb[c * NG + g] : 0u;
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
             const uint32_t nq = nk[q];

@@ -149,10 +149,10 @@ struct mhdpic_ctx {
     // current one's, and the push that reads it has not run yet
     bool map_pending = false;
     // where the particles of a step move to their new slots
-    // (mhdpic_set_particle_moves); automatic: in the push for 3D boxes
+    // (mhdpic_set_particle_moves); automatic: in the push
     int32_t moves = MHDPIC_MOVES_AUTO;
     bool moves_in_push() const {
-        return moves == MHDPIC_MOVES_IN_PUSH || (moves == MHDPIC_MOVES_AUTO && ndim == 3);
+        return moves != MHDPIC_MOVES_IN_BINNING;
     }
     int it = 0;    // which work list describes that buffer
     int nj = 0;    // which nJ buffer is current
