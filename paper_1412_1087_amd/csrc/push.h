@@ -194,16 +194,15 @@ __device__ __forceinline__ void field_store(float* F, int NFF, int c, const floa
     }
 }
 
-// One particle's stored state (in 2D the third offset reads as 0), read for
-// slot jd from the slot the binning's map names, if it left one.
+// One particle's stored state (in 2D the third offset reads as 0), read from
+// slot j.
 template <int NDIM, typename R>
 struct PartRec {
     uint32_t cell = 0;
     R d[3] = {R(0), R(0), R(0)}, v[3] = {R(0), R(0), R(0)};
     R m = R(0), qm = R(0);
     template <typename PS>
-    __device__ __forceinline__ void load(const PS& P, const uint32_t* map, int jd) {
-        const int j = map ? (int)map[jd] : jd;
+    __device__ __forceinline__ void load(const PS& P, int j) {
         cell = P.cell[j];
         d[0] = P.d[0][j];
         d[1] = P.d[1][j];
@@ -247,6 +246,12 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     const WorkItem w = a.items[item];
     const BoxDev bx = a.boxes[w.box];  // a copy: kept in registers across the stores
     if (a.grp >= 0 && bx.grp != a.grp) return;  // a box of another tile shape
+    // the slot that holds the particle of slot jd (the binning's map, if it
+    // left one); each one is read an iteration ahead of its particle, the
+    // first before the fields are staged
+    auto src_of = [&](int jd) { return a.map ? (int)a.map[jd] : jd; };
+    const int j0 = w.begin + (int)threadIdx.x;
+    int src = j0 < w.end ? src_of(j0) : 0;
     int tx, ty, tz;
     tile_coords<NDIM>(bx, w.tile, tx, ty, tz);
     const int ox = tile_origin(bx, 0, tx, TX), oy = tile_origin(bx, 1, ty, TY);
@@ -282,14 +287,21 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     // have no registers to spare for it
     constexpr bool kPrefetch = PushShape<Pol, NDIM>::PREFETCH;
     PartRec<NDIM, R> nxt;
-    if (kPrefetch && w.begin + (int)threadIdx.x < w.end) nxt.load(a.Psrc, a.map, w.begin + (int)threadIdx.x);
-    for (int j = w.begin + (int)threadIdx.x; j < w.end; j += BLOCK) {
+    if (kPrefetch && j0 < w.end) {
+        nxt.load(a.Psrc, src);
+        if (j0 + BLOCK < w.end) src = src_of(j0 + BLOCK);
+    }
+    for (int j = j0; j < w.end; j += BLOCK) {
         PartRec<NDIM, R> cur;
         if (kPrefetch) {
             cur = nxt;
-            if (j + BLOCK < w.end) nxt.load(a.Psrc, a.map, j + BLOCK);
+            if (j + BLOCK < w.end) {
+                nxt.load(a.Psrc, src);
+                if (j + 2 * BLOCK < w.end) src = src_of(j + 2 * BLOCK);
+            }
         } else {
-            cur.load(a.Psrc, a.map, j);
+            cur.load(a.Psrc, src);
+            if (j + BLOCK < w.end) src = src_of(j + BLOCK);
         }
         int i[3];
         unpack_cell<NDIM>(cur.cell, i[0], i[1], i[2]);
