@@ -523,9 +523,10 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred, int grp) {
     using R = typename Pol::R;
     const Layout& L = c->L;
     PushArgsT<Pol> a;
-    a.Psrc = part<typename Pol::Part, R>(c, c->cur);
+    const int dst = c->map_pending ? 1 - c->cur : c->cur;
+    a.P = part<typename Pol::Part, R>(c, dst);
+    a.src_delta = (int64_t)(c->cur == 0 ? L.partA : L.partB) - (int64_t)(dst == 0 ? L.partA : L.partB);
     a.map = c->map_pending ? at<uint32_t>(c, L.key) : nullptr;
-    a.P = part<typename Pol::Part, R>(c, c->map_pending ? 1 - c->cur : c->cur);
     a.code = at<uint16_t>(c, L.code);
     a.cnt = at<uint32_t>(c, L.cnt);
     a.EB = at<R>(c, L.EB);

@@ -22,10 +22,11 @@ namespace mhdpic {
 
 template <class Pol>
 struct PushArgsT {
-    typename Pol::Part Psrc;     // the particles before this push
-    const uint32_t* map;         // slot j of P -> slot of its particle in Psrc; NULL:
-                                 // Psrc is P and the particles are updated in place
     typename Pol::Part P;        // out: tile-sorted particles (the ids already there)
+    int64_t src_delta;           // bytes from each array of P to the same array of the
+                                 // buffer the particles are read from (0: in place)
+    const uint32_t* map;         // slot j of P -> slot of its particle in that buffer;
+                                 // NULL: slot j itself
     uint16_t* code;              // out: code word (pack_code)
     uint32_t* cnt;               // out: [item][code] particle counts
     const typename Pol::R* EB;   // [cells][6] E and B
@@ -194,24 +195,32 @@ __device__ __forceinline__ void field_store(float* F, int NFF, int c, const floa
     }
 }
 
+// Array p of another particle buffer of the same layout, delta bytes away
+// (the two buffers of a context share one layout, so one offset serves every
+// array and the kernel holds one set of array addresses).
+template <typename T>
+__device__ __forceinline__ const T* other_buffer(const T* p, int64_t delta) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + delta);
+}
+
 // One particle's stored state (in 2D the third offset reads as 0), read from
-// slot j.
+// slot j of the buffer delta bytes away from P.
 template <int NDIM, typename R>
 struct PartRec {
     uint32_t cell = 0;
     R d[3] = {R(0), R(0), R(0)}, v[3] = {R(0), R(0), R(0)};
     R m = R(0), qm = R(0);
     template <typename PS>
-    __device__ __forceinline__ void load(const PS& P, int j) {
-        cell = P.cell[j];
-        d[0] = P.d[0][j];
-        d[1] = P.d[1][j];
-        d[2] = NDIM == 3 ? P.d[2][j] : R(0);
-        v[0] = P.v[0][j];
-        v[1] = P.v[1][j];
-        v[2] = P.v[2][j];
-        m = P.m[j];
-        qm = P.qm[j];
+    __device__ __forceinline__ void load(const PS& P, int64_t delta, int j) {
+        cell = other_buffer(P.cell, delta)[j];
+        d[0] = other_buffer(P.d[0], delta)[j];
+        d[1] = other_buffer(P.d[1], delta)[j];
+        d[2] = NDIM == 3 ? other_buffer(P.d[2], delta)[j] : R(0);
+        v[0] = other_buffer(P.v[0], delta)[j];
+        v[1] = other_buffer(P.v[1], delta)[j];
+        v[2] = other_buffer(P.v[2], delta)[j];
+        m = other_buffer(P.m, delta)[j];
+        qm = other_buffer(P.qm, delta)[j];
     }
 };
 
@@ -288,19 +297,24 @@ __global__ void __launch_bounds__(BLOCK, (PushShape<Pol, NDIM>::WAVES)) k_push(P
     constexpr bool kPrefetch = PushShape<Pol, NDIM>::PREFETCH;
     PartRec<NDIM, R> nxt;
     if (kPrefetch && j0 < w.end) {
-        nxt.load(a.Psrc, src);
+        nxt.load(a.P, a.src_delta, src);
         if (j0 + BLOCK < w.end) src = src_of(j0 + BLOCK);
     }
     for (int j = j0; j < w.end; j += BLOCK) {
+        // the offset is re-read each iteration, so the read addresses are
+        // formed where they are used instead of being held in (spilled)
+        // scalar registers for the whole loop
+        int64_t delta = a.src_delta;
+        asm volatile("" : "+s"(delta));
         PartRec<NDIM, R> cur;
         if (kPrefetch) {
             cur = nxt;
             if (j + BLOCK < w.end) {
-                nxt.load(a.Psrc, src);
+                nxt.load(a.P, delta, src);
                 if (j + 2 * BLOCK < w.end) src = src_of(j + 2 * BLOCK);
             }
         } else {
-            cur.load(a.Psrc, src);
+            cur.load(a.P, delta, src);
             if (j + BLOCK < w.end) src = src_of(j + BLOCK);
         }
         int i[3];
