@@ -96,7 +96,9 @@ typedef struct {
                                (App. A.4); mhdpic_step rejects C*|dt|/dx above it */
     int32_t tile[3];        /* cells per tile per dimension for the LDS-staged kernels
                                (the boxes of one context may differ);
-                               0 = library default.  tile[2] is ignored in 2D */
+                               0 = library default (2D: 32x16; 3D: 8x4x4, or
+                               4x4x4 for a box given 24 or more particles per
+                               cell).  tile[2] is ignored in 2D */
     int32_t boundary[3][2]; /* per axis, low and high face: MHDPIC_PERIODIC (both faces or
                                neither), MHDPIC_REFLECT or MHDPIC_ABSORB; all zero =
                                periodic.  A non-periodic axis needs at least 2 cells */
