@@ -431,11 +431,14 @@ int launch_bin(mhdpic_ctx* c, hipStream_t s, int keys) {
     // to old ones, through which the push reads the particles and writes them,
     // updated, to the other buffer; a compaction always moves them itself
     const bool map = keys != kKeysStay && c->moves_in_push();
-    auto kern = L.tagged ? (map ? k_bin_scatter_class<NDIM, PS, 256, true, true>
+    // (moving only ids, a block needs few registers: twice the threads per item
+    // hide more of the ranking's latency)
+    constexpr int BM = 512;
+    auto kern = L.tagged ? (map ? k_bin_scatter_class<NDIM, PS, BM, true, true>
                                 : k_bin_scatter_class<NDIM, PS, 256, true, false>)
-                         : (map ? k_bin_scatter_class<NDIM, PS, 256, false, true>
+                         : (map ? k_bin_scatter_class<NDIM, PS, BM, false, true>
                                 : k_bin_scatter_class<NDIM, PS, 256, false, false>);
-    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(256), 0, s, A, Bo, at<uint16_t>(c, L.code),
+    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(map ? BM : 256), 0, s, A, Bo, at<uint16_t>(c, L.code),
                        at<uint32_t>(c, L.off), at<WorkItem>(c, L.items[it]),
                        at<uint32_t>(c, L.n_items[it]), at<uint32_t>(c, L.key));
     if (map)
