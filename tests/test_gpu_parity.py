@@ -401,3 +401,16 @@ def test_particle_moves_rejects_unknown_setting():
     g = DeviceRun(W.gyro2d(nx=8, ny=8, ppc=2, seed=65))
     with pytest.raises(M.MhdpicError):
         g.ctx.set_particle_moves(3)
+
+
+def test_parity_3d_long_run_stays_bit_exact():
+    # 200 steps of a small beam box: particles cross tiles and the periodic
+    # wrap many times, with the particles moved by the push through the map
+    _parity(W.bell3d(n=(12, 10, 9), ppc=4, seed=66, hall=1), n_steps=200, steps_per_call=50)
+
+
+def test_parity_2d_dense_band_long_run_stays_bit_exact():
+    # a dense band (tiles of several work items) over 120 steps, the
+    # particles moved by the push in chunked level order
+    _parity(W.shock2d(nx=128, ny=32, n_particles=128 * 32 * 6, seed=67), n_steps=120,
+            steps_per_call=40)
