@@ -26,6 +26,21 @@ def test_algorithmic_bytes_of_the_push():
     assert c["per_particle"] == (4 + 12 + 12 + 8) + (4 + 12 + 12)
 
 
+def test_algorithmic_bytes_when_the_push_moves_the_particles():
+    # the push also reads the slot map (4) and writes m and q/mc at the new
+    # slot (2 * msz)
+    a = bench.algorithmic_bytes(3, 4_194_304, 64 ** 3, moves_in_push=True)
+    assert a["per_particle"] == 140 and a["per_cell"] == 144
+    assert a["per_launch"] == 4_194_304 * 140 + 64 ** 3 * 144
+    b = bench.algorithmic_bytes(2, 16_777_216, 8192 * 32, moves_in_push=True)
+    assert b["per_particle"] == 124
+    c = bench.algorithmic_bytes(3, 10, 0, fsz=4, msz=4, moves_in_push=True)
+    assert c["per_particle"] == 76
+    # the library moves the particles in the push unless told otherwise
+    assert bench.moves_in_push(3, 0) and bench.moves_in_push(2, 0) and bench.moves_in_push(2, 2)
+    assert not bench.moves_in_push(3, 1)
+
+
 def test_stored_traffic_follows_the_kernel_sources(monkeypatch, tmp_path):
     label = "bell3d-64^3-ppc16-hall"
     prof = tmp_path / "profiles"
