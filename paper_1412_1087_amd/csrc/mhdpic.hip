@@ -8,6 +8,7 @@
 //                                     also counts particles per next tile
 //     scan -> scatter (not after the last step)
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -154,6 +155,8 @@ struct mhdpic_ctx {
     Layout L;
     unsigned char* ws = nullptr;
     int cur = 0;   // which particle buffer (0 = A, 1 = B) holds the state
+    // events a timed push launch records (PhaseTimer)
+    hipEvent_t push_ev[2] = {nullptr, nullptr};
     // a binning has left the map from the other buffer's slots to the
     // current one's, and the push that reads it has not run yet
     bool map_pending = false;
@@ -564,7 +567,14 @@ int launch_push_pol(mhdpic_ctx* c, hipStream_t s, bool do_pred, int grp) {
         HIP_TRY(hipEventCreateWithFlags(&e1, kTimingEventFlags));
         HIP_TRY(hipEventRecord(e0, s));
     }
-    hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s, a);
+    // a timed push carries its phase's events in the launch (start on the
+    // first launch group, end on the last)
+    const int last = (int)c->grp_shape.size() - 1;
+    hipEvent_t ev0 = grp == 0 ? c->push_ev[0] : nullptr, ev1 = grp == last ? c->push_ev[1] : nullptr;
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), (uint32_t)lds, s, ev0, ev1, 0, a);
+    else
+        hipLaunchKernelGGL(kern, dim3(item_grid(L)), dim3(BLOCK), lds, s, a);
     if (c->grp_timing) {
         HIP_TRY(hipEventRecord(e1, s));
         c->grp_marks.push_back({grp, e0, e1});
@@ -706,15 +716,30 @@ struct PhaseTimer {
         if (hipEventCreateWithFlags(&e, kTimingEventFlags) != hipSuccess) return nullptr;
         return e;
     }
-    PhaseTimer(mhdpic_ctx* c_, hipStream_t s_, int phase_) : c(c_), s(s_), phase(phase_) {
+    // in_launch: the phase's kernels take the events themselves (the first
+    // launch its start, the last its end: mhdpic_ctx::push_ev), so no event
+    // is recorded between kernels
+    bool in_launch = false;
+    PhaseTimer(mhdpic_ctx* c_, hipStream_t s_, int phase_, bool in_launch_ = false)
+        : c(c_), s(s_), phase(phase_), in_launch(in_launch_) {
         if (!((c->timing >> phase) & 1u)) return;
         a = take();
         b = take();
-        if (a && b) (void)hipEventRecord(a, s);
+        if (!a || !b) return;
+        if (in_launch) {
+            c->push_ev[0] = a;
+            c->push_ev[1] = b;
+        } else {
+            (void)hipEventRecord(a, s);
+        }
     }
     ~PhaseTimer() {
         if (!((c->timing >> phase) & 1u) || !a || !b) return;
-        (void)hipEventRecord(b, s);
+        if (in_launch) {
+            c->push_ev[0] = c->push_ev[1] = nullptr;
+        } else {
+            (void)hipEventRecord(b, s);
+        }
         c->marks.push_back({phase, a, b});
     }
 };
@@ -816,7 +841,7 @@ int enqueue_steps(mhdpic_ctx* c, const double* B, const double* vg, const double
         for (int sub = 0; sub < n_sub && !rc; ++sub) {
             const bool last_sub = sub + 1 == n_sub;
             {
-                PhaseTimer t(c, s, 2);
+                PhaseTimer t(c, s, 2, true);
                 rc = launch_push(c, s, last_sub);
             }
             if (rc) break;
