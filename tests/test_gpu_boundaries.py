@@ -321,3 +321,38 @@ def test_position_outside_a_non_periodic_axis_rejected():
         M.Context([gpu_box(spec, boundary=((R, R), (P, P), (P, P)))], [1], to_dev(x),
                   to_dev(np.zeros((3, 1))), to_dev(np.ones(1)), to_dev(np.ones(1)))
     assert e.value.code == M.ERANGE
+
+
+@pytest.mark.parametrize("moves", [1, 2], ids=["moves_in_binning", "moves_in_push"])
+def test_injection_removal_and_compaction_3d_match_oracle(moves):
+    """A 3D box with a reflecting and an absorbing face: tagged injections
+    between steps, removal by tag, and an injection that needs the removed
+    slots (a compaction first), with the ids and tags moved along."""
+    _need_gpu()
+    rng = np.random.default_rng(86)
+    spec = W.BoxSpec(ndim=3, n=(20, 9, 10), dx=(0.5, 2.0, 1.25), x0=(-3.7, 11.2, 0.5), C=20.0, hall=1)
+    lo = np.array(spec.x0)[:, None]
+    ext = (np.array(spec.n) * np.array(spec.dx))[:, None]
+
+    def batch(n, t):
+        x = lo + rng.uniform(0.0, 1.0, (3, n)) * ext
+        v = rng.normal(0.0, 5.0, (3, n))
+        return x, v, np.full(n, 2e-3), np.ones(n), np.full(n, t)
+
+    x0, v0, m0, q0, _ = batch(3000, 0.0)
+    B, vg, rho = _fields(spec, (0.4, 0.1, 1.0), (0.3, 0.0, 0.1), rng, 0.05)
+    p = Pair(spec, ((R, A), (P, P), (P, P)), x0, v0, m0, q0, B, vg, rho, capacity=5200, moves=moves)
+    dt = 0.04
+    p.inject(*batch(900, 0.1))
+    p.step(dt, 2)
+    p.inject(*batch(900, 0.2))
+    p.check("two tagged injections")
+    p.step(dt, 1)
+    assert p.remove_tagged(0.15, 0.5) > 0
+    p.check("after removal")
+    # 4800 slots in use (the removed ones included) + 1100 > 5200: the
+    # injection first compacts the store
+    p.inject(*batch(1100, 0.3))
+    p.check("injection into reclaimed slots")
+    p.step(dt, 3)
+    p.check("end")
